@@ -1,0 +1,236 @@
+"""Benchmark: solves/sec to a 1e-6 relative residual on a 128^3 mixed-BC scene,
+mixed precision vs FP32, with p50/p99 solve latency.
+
+A step is one whole solve (Alg. 1 with the network of Alg. 2 as
+preconditioner) of one synthetic 128^3 system whose labels, right-hand side
+and weights are already resident in HBM.  The headline `value` is the mixed
+path (bf16/fp16 network, fp32 Krylov vectors, fp64 refinement); the plain
+FP32 path is timed on the same inputs and reported beside it.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Also reports the roofline of the dominant kernel
+(HIP-event durations recorded by the library on its launch stream, over a
+profiled pass of the same solves) and the CPU oracle timed on a bounded
+sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--size", type=int, default=128)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=2000)
+    ap.add_argument("--headline", default="mixed_bf16", choices=["mixed_bf16", "mixed_fp16", "fp32", "fp64"])
+    ap.add_argument("--compare", default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations in the CPU sample")
+    return ap.parse_args()
+
+
+# Algorithmic HBM bytes per cell of each kernel (compulsory traffic of the
+# method, labels-only operator reads), with s = bytes per vector element and
+# xs = bytes per solution element (8 in the mixed modes, where x is double):
+#   net_down_l1   x, d, b (8), labels -> x, r, x1, pooled r
+#                 (x + alpha d, r = b - A x, CConv_1, pool)   2 xs + (3 + 1/8) s + 9
+#   net_up_l1     x2 (1/8), labels, x1, n_prev Ad -> dhat      (2 + 1/8 + n_prev) s + 1
+#   ortho_matvec  dhat, n_prev d, r, labels -> d, Ad           (4 + n_prev) s + 1
+#   net_down / net_up (coarse levels): 4 B of packed counts instead of 1 B labels
+def alg_bytes_per_cell(kernel: str, s: int, xs: int = None, n_prev: int = 2) -> float | None:
+    xs = s if xs is None else xs
+    table = {
+        "net_down_l1": 2 * xs + 3.125 * s + 9,
+        "net_up_l1": (2.125 + n_prev) * s + 1,
+        "ortho_matvec": (4 + n_prev) * s + 1,
+        "net_down": 2.125 * s + 4,
+        "net_up": 2.125 * s + 4,
+        "net_coarsest": 2 * s + 4,
+    }
+    return table.get(kernel)
+
+
+def iteration_bytes_per_fine_cell(s: int, xs: int, n_prev: int = 2) -> float:
+    """All per-iteration kernels, coarse levels weighted by their 1/8^(l-1) share."""
+    coarse = sum(8.0 ** -(l - 1) for l in range(2, 7))
+    return (alg_bytes_per_cell("net_down_l1", s, xs) + alg_bytes_per_cell("net_up_l1", s, xs, n_prev)
+            + alg_bytes_per_cell("ortho_matvec", s, xs, n_prev)
+            + coarse * (alg_bytes_per_cell("net_down", s) + alg_bytes_per_cell("net_up", s)))
+
+
+def cpu_baseline(labels, b, params, iters_sample):
+    """The FP64 oracle on one host core: setup + `iters_sample` iterations,
+    scaled to a whole solve with the oracle's own iteration count."""
+    from threadpoolctl import threadpool_limits
+    from oracle import network as onet
+    from oracle import npsdo as onpsdo
+
+    ref_path = os.path.join(ROOT, "tests", "golden", "oracle_workloads.json")
+    ref = json.load(open(ref_path)).get(f"{labels.shape[0]}^3") if os.path.exists(ref_path) else None
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        net = onet.Network(params, 6, labels)
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        res = onpsdo.solve(labels, b, net.apply, max_iter=iters_sample, fixed_iters=True)
+        t_iter = (time.perf_counter() - t0) / max(res.iterations, 1)
+    if ref is None:
+        return None
+    t_solve = t_setup + ref["iterations"] * t_iter
+    return {"value": 1.0 / t_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle setup + {iters_sample} NPSDO iterations at {labels.shape[0]}^3 on 1 thread "
+                      f"({t_setup:.1f} s + {t_iter:.2f} s/iteration), scaled to the oracle's own "
+                      f"{ref['iterations']}-iteration solve of this workload"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: this solver runs a single solve per GPU and the build has "
+              f"no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import nps_inputs as gi
+    import paper_2310_00177_amd as nps
+    from paper_2310_00177_amd import _lib
+
+    prec_of = {"mixed_bf16": nps.MIXED_BF16, "mixed_fp16": nps.MIXED_FP16, "fp32": nps.FP32, "fp64": nps.FP64}
+    torch.cuda.set_device(0)
+    n = args.size
+    spec = gi.scene_c1() if n == 32 else gi.scene_serving(n)
+    lab = gi.gen_labels(spec, seed=args.seed)
+    b = gi.gen_rhs(lab, seed=args.seed + 1)
+    params = gi.multilevel_params(6)
+    labels_d = torch.from_numpy(lab).cuda()
+    b_d = torch.from_numpy(b).cuda()
+    net = nps.Net(params, 6)
+    print(f"# workload {n}^3, fluid {int((lab == 0).sum())} cells", file=sys.stderr, flush=True)
+
+    def run(name, steps, warmup):
+        prec = prec_of[name]
+        ws = nps.workspace(lab.shape, 6, prec, 2)
+        x = torch.empty_like(b_d)
+        for _ in range(warmup):
+            nps.solve(net, labels_d, b_d, tol=args.tol, max_iter=args.max_iter, precision=prec, x=x, ws=ws)
+        torch.cuda.synchronize()
+        lat = []
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s0 = time.perf_counter()
+            _, info = nps.solve(net, labels_d, b_d, tol=args.tol, max_iter=args.max_iter, precision=prec,
+                                x=x, ws=ws)
+            lat.append(time.perf_counter() - s0)   # nps_solve synchronises its stream
+            infos.append(info)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+        lat_ms = np.array(lat) * 1e3
+        its = [i.iterations for i in infos]
+        ok = all(i.status == 0 and i.rel_residual < args.tol for i in infos)
+        print(f"# {name}: {steps / total:.2f} solves/s, {total / steps * 1e3:.2f} ms/solve, iterations {its[0]}, "
+              f"true rel residual {infos[-1].rel_residual:.2e}, converged {ok}", file=sys.stderr, flush=True)
+        return {"solves_per_s": steps / total, "ms_per_solve": total / steps * 1e3,
+                "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+                "iterations": int(np.median(its)), "rel_residual_true": max(i.rel_residual for i in infos),
+                "converged": ok, "refinements": infos[-1].refinements}, ws, x
+
+    head, ws_h, x_h = run(args.headline, args.steps, args.warmup)
+    comp = None
+    if args.compare and args.compare != args.headline:
+        comp, _, _ = run(args.compare, args.steps, args.warmup)
+
+    # profiled pass: per-kernel durations from HIP events on the launch stream
+    prec = prec_of[args.headline]
+    s_bytes = 8 if prec == nps.FP64 else 4
+    x_bytes = 4 if prec == nps.FP32 else 8
+    _lib.nps_profile_enable(1)
+    prof_solves = max(2, min(args.steps, 5))
+    t_iter_sum, its_sum = 0.0, 0
+    for _ in range(prof_solves):
+        _, info = nps.solve(net, labels_d, b_d, tol=args.tol, max_iter=args.max_iter, precision=prec, x=x_h, ws=ws_h)
+        its_sum += info.iterations
+    rc, stats = _lib.nps_profile_read(64)
+    _lib.nps_profile_enable(0)
+    kstats = {s.name.decode(): (s.launches, s.total_ms, s.cells) for s in stats}
+    per_iter_ms = sum(v[1] for k, v in kstats.items() if not k.startswith("setup") and k not in ("state_init", "finalize")) / max(its_sum, 1)
+    dom = max((k for k in kstats if alg_bytes_per_cell(k, s_bytes) is not None), key=lambda k: kstats[k][1])
+    launches, total_ms, cells = kstats[dom]
+    avg_s = total_ms / launches * 1e-3
+    bytes_per_launch = alg_bytes_per_cell(dom, s_bytes, x_bytes) * cells / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    it_bytes = iteration_bytes_per_fine_cell(s_bytes, x_bytes) * lab.size
+    kernels = {k: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3, "share": v[1] / sum(w[1] for w in kstats.values())}
+               for k, v in kstats.items()}
+    print("# kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us x{v['launches']} ({v['share'] * 100:.1f}%)"
+                                    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["share"])),
+          file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(lab, b, params, args.cpu_iters)
+
+    dtype = {"mixed_bf16": "bf16+f32+f64", "mixed_fp16": "f16+f32+f64", "fp32": "f32", "fp64": "f64"}[args.headline]
+    out = {
+        "metric": "solves/sec to 1e-6 rel. residual at 128^3, mixed vs FP32; p50/p99 latency",
+        "value": head["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": f"{n}^3 mixed-BC voxel scene (20 solid spheres r 4-20, 3 slabs, solid walls, flat free "
+                        f"surface drawn in [64,112]), N(0,1) RHS on fluid, tol {args.tol:g}, L=6, n_ortho=2",
+            "precision": args.headline,
+            "weights": "multilevel (hand-set blob in the paper's architecture; seeded Xavier weights do not "
+                       "precondition: the iteration stalls)",
+            "iterations": head["iterations"],
+            "rel_residual_true": head["rel_residual_true"],
+            "converged": head["converged"],
+        },
+        "p50_ms": head["p50_ms"],
+        "p99_ms": head["p99_ms"],
+        "compare": None if comp is None else {
+            "precision": args.compare, "value": comp["solves_per_s"], "p50_ms": comp["p50_ms"],
+            "p99_ms": comp["p99_ms"], "iterations": comp["iterations"],
+            "rel_residual_true": comp["rel_residual_true"], "converged": comp["converged"],
+            "speedup_headline_vs_compare": head["solves_per_s"] / comp["solves_per_s"]},
+        "roofline": {
+            "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
+            "iteration": {"alg_bytes": it_bytes, "us": per_iter_ms * 1e3,
+                          "achieved_GBs": it_bytes / (per_iter_ms * 1e-3) / 1e9,
+                          "frac": it_bytes / (per_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+        },
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,168 @@
+/*
+ * nps.h -- C ABI of the MI355X neural-preconditioned Poisson solver.
+ *
+ * The library solves the reduced pressure Poisson system A~ x~ = b~ of a
+ * voxel grid whose cells are labelled fluid / air (Dirichlet, p = 0) / solid
+ * (Neumann), with the NPSDO iteration (Alg. 1 of arXiv 2310.00177: steepest
+ * descent on the network-preconditioned residual, A-orthogonalised against
+ * the last n_ortho directions, exact line search) and the spatially-varying-
+ * kernel network of Alg. 2 (CConv and Aff blocks of Sec. "Architecture",
+ * extended to 3D) as the preconditioner.  The matrix is never formed: it is
+ * implied by the labels (Sec. "Spatial Discretization").
+ *
+ * Conventions shared by every entry point
+ *   - Grids are (nz, ny, nx) arrays, x fastest, row-major, no padding.
+ *   - Labels are uint8: 0 FLUID, 1 AIR, 2 SOLID.  Cells outside the grid are
+ *     solid.  Vectors are full-grid; entries outside fluid are ignored on
+ *     input and written as zero on output (pad/unpad rule of Sec. "Neural
+ *     Preconditioner").
+ *   - Pointers ending in _d are device pointers (HBM of the current HIP
+ *     device); pointers ending in _h are host pointers.  The caller owns every
+ *     buffer; the library keeps no pointer after a call returns, except the
+ *     device buffer handed to nps_net_create, which must outlive the net.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Calls enqueue work on
+ *     it; nps_solve synchronises with it before returning, the parity hooks
+ *     do not.
+ *   - No solve-path call allocates device memory: scratch comes from the
+ *     caller's workspace, sized by nps_workspace_bytes.
+ *   - Return value: NPS_OK (0), a soft status (> 0: outputs valid), or a
+ *     hard error (< 0: outputs untouched).  nps_last_error() returns a
+ *     thread-local message for the last failure.
+ */
+#ifndef NPS_H
+#define NPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum nps_status {
+    NPS_OK = 0,
+    NPS_NOT_CONVERGED = 1,   /* max_iter reached: x holds the last iterate   */
+    NPS_EINVAL = -1,         /* bad argument (null pointer, tol <= 0, ...)    */
+    NPS_ESHAPE = -2,         /* a dimension not divisible by 2^(levels-1)     */
+    NPS_ELABEL = -3,         /* a label outside {0, 1, 2}                     */
+    NPS_ENOFLUID = -4,       /* no fluid cell                                 */
+    NPS_ENONFINITE = -5,     /* NaN or Inf in b on a fluid cell               */
+    NPS_EBREAKDOWN = -6,     /* d.Ad <= 0 or not finite: no descent direction */
+    NPS_ENOMEM = -7,         /* workspace or device buffer too small          */
+    NPS_EDEVICE = -8         /* a HIP runtime call failed                     */
+};
+
+enum nps_label { NPS_FLUID = 0, NPS_AIR = 1, NPS_SOLID = 2 };
+
+/* Arithmetic of the network and the Krylov vectors.
+ *   NPS_FP64        everything in double.
+ *   NPS_FP32        network and Krylov vectors in float; dot products
+ *                   accumulate in double; the exit test uses the true
+ *                   residual b - A x evaluated in double.
+ *   NPS_MIXED_BF16  network kernels generated on bf16 matrix cores with fp32
+ *   NPS_MIXED_FP16  accumulation (fp16 for the _FP16 variant), Krylov vectors
+ *                   in float, the solution accumulated in double with a
+ *                   double-precision true-residual refinement every
+ *                   refine_every iterations.                                 */
+enum nps_precision { NPS_FP64 = 0, NPS_FP32 = 1, NPS_MIXED_BF16 = 2, NPS_MIXED_FP16 = 3 };
+
+typedef struct { int nz, ny, nx; } nps_dims;
+
+typedef struct {
+    double tol;          /* stop when ||b - A x||_2 < tol * ||b||_2 (> 0)             */
+    int max_iter;        /* iteration cap (>= 0)                                      */
+    int n_ortho;         /* directions to A-orthogonalise against, 0..4 (paper: 2)    */
+    int precision;       /* enum nps_precision                                        */
+    int refine_every;    /* mixed modes: FP64 refinement period (0 = only at exit)    */
+    int fixed_iters;     /* 1: run exactly max_iter iterations, no convergence test    */
+} nps_opts;
+
+typedef struct {
+    int iterations;              /* NPSDO iterations performed                        */
+    int status;                  /* same code nps_solve returned                      */
+    double rel_residual;         /* true ||b - A x|| / ||b|| at exit, in double       */
+    double rel_residual_rec;     /* the iteration's own (recursive) residual estimate */
+    int refinements;             /* true-residual recomputations performed            */
+    int n_fluid;                 /* number of fluid cells                              */
+} nps_info;
+
+typedef struct nps_net nps_net;
+
+/* Number of parameters of an L-level network: (2L-1) CConv blocks of
+ * 27*81 weights + 27 biases and 2(L-1) Aff blocks of 81 weights + 1 bias
+ * (25,174 at L = 6, the "~25k" of Sec. "Architecture"). */
+size_t nps_param_count(int levels);
+
+/* Device bytes nps_net_create needs for an L-level network. */
+size_t nps_net_bytes(int levels);
+
+/* Build a network from a float64 host blob of nps_param_count(levels)
+ * entries, laid out (Alg. 2 block order):
+ *   for l = 1..L   CConv_1^l: W[27][3][3][3][3], B[27]
+ *   for l = 1..L-1 CConv_2^l: W, B
+ *   for l = 1..L-1 Aff_1^l: Wbar[3][3][3][3], Bbar;  Aff_2^l: Wbar, Bbar
+ * W[t][c][oz+1][oy+1][ox+1]: t = 9(az+1) + 3(ay+1) + (ax+1) is the kernel tap
+ * applied to r(p + a), c the image channel, o the image-window offset.
+ * levels must be 2..6.  The preprocessed weights are copied into dev_buf
+ * (nps_net_bytes(levels) bytes, 256-byte aligned) on `stream`; the blob may
+ * be freed on return.  *out is a host handle released by nps_net_destroy. */
+int nps_net_create(const double* params_h, size_t n_params, int levels,
+                   void* dev_buf_d, size_t dev_bytes, void* stream, nps_net** out);
+void nps_net_destroy(nps_net* net);
+int nps_net_levels(const nps_net* net);
+
+/* Workspace bytes for nps_solve / nps_apply_precond at these dims. */
+size_t nps_workspace_bytes(nps_dims dims, int levels, int precision, int n_ortho);
+
+/* Solve A~ x~ = b~ (Alg. 1 with the network of Alg. 2 as preconditioner).
+ *   labels_d  uint8[nz*ny*nx]   cell labels.
+ *   b_d       double[nz*ny*nx]  right-hand side (read on fluid cells only).
+ *   x_d       double[nz*ny*nx]  solution, written on every cell (0 off fluid).
+ *   x0 = 0.  Precondition: every fluid component touches an air cell
+ *   (otherwise A~ is singular and the iteration reports NPS_EBREAKDOWN or
+ *   NPS_NOT_CONVERGED).  b = 0 gives x = 0 after 0 iterations.
+ *   On NPS_OK / NPS_NOT_CONVERGED, x_d and *info are valid.  On
+ *   NPS_EBREAKDOWN x_d holds the last iterate.  The stream is synchronised. */
+int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims,
+              const double* b_d, double* x_d, const nps_opts* opts, nps_info* info,
+              void* ws_d, size_t ws_bytes, void* stream);
+
+/* Parity hook: y = A x, the mixed-BC 7-point matrix of Sec. "Spatial
+ * Discretization" (diagonal = number of fluid or air face neighbours,
+ * -1 per fluid face neighbour, zero rows off fluid).  precision NPS_FP64:
+ * x_d, y_d are double; NPS_FP32: float.  Not synchronised. */
+int nps_apply_laplacian(const uint8_t* labels_d, nps_dims dims, const void* x_d, void* y_d,
+                        int precision, void* stream);
+
+/* Parity hook: d = P(I, r), one evaluation of the network (Alg. 2) with the
+ * same kernels nps_solve uses.  precision NPS_FP64: r_d, d_d double; all
+ * other precisions: float.  The workspace is sized by nps_workspace_bytes
+ * with the same dims/levels/precision.  Not synchronised. */
+int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims,
+                      const void* r_d, void* d_d, int precision,
+                      void* ws_d, size_t ws_bytes, void* stream);
+
+/* Per-kernel timing.  While enabled (on != 0, per calling thread), every
+ * kernel the library launches is bracketed by a pair of HIP events recorded
+ * on the launch stream.  nps_profile_read synchronises those events, writes
+ * one record per kernel name (at most max_records, in first-launch order)
+ * to out_h, stores the number of names in *n_records, and clears the
+ * accumulated records.  Returns NPS_ENOMEM if more than 1,000,000 launches
+ * were recorded since the last read (later ones are dropped). */
+typedef struct {
+    char name[40];        /* kernel name, e.g. "net_down_l1"               */
+    int launches;         /* launches recorded                             */
+    double total_ms;      /* sum of event-to-event durations               */
+    double cells;         /* sum over launches of the cells of the level   */
+} nps_kernel_stat;
+
+int nps_profile_enable(int on);
+int nps_profile_read(nps_kernel_stat* out_h, int max_records, int* n_records);
+
+/* Thread-local description of the last error ("" if none). */
+const char* nps_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NPS_H */

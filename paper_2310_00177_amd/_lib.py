@@ -1,0 +1,135 @@
+"""ctypes binding of libnps.so: one Python function per C-ABI entry point,
+same names, argument marshalling only (the declarations live in include/nps.h).
+
+Importing this module loads the library; if libnps.so is missing it raises,
+so nothing silently falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnps.so")
+
+# enum nps_status
+NPS_OK, NPS_NOT_CONVERGED = 0, 1
+NPS_EINVAL, NPS_ESHAPE, NPS_ELABEL, NPS_ENOFLUID = -1, -2, -3, -4
+NPS_ENONFINITE, NPS_EBREAKDOWN, NPS_ENOMEM, NPS_EDEVICE = -5, -6, -7, -8
+# enum nps_precision
+NPS_FP64, NPS_FP32, NPS_MIXED_BF16, NPS_MIXED_FP16 = 0, 1, 2, 3
+# enum nps_label
+NPS_FLUID, NPS_AIR, NPS_SOLID = 0, 1, 2
+
+STATUS_NAMES = {
+    0: "NPS_OK", 1: "NPS_NOT_CONVERGED", -1: "NPS_EINVAL", -2: "NPS_ESHAPE", -3: "NPS_ELABEL",
+    -4: "NPS_ENOFLUID", -5: "NPS_ENONFINITE", -6: "NPS_EBREAKDOWN", -7: "NPS_ENOMEM", -8: "NPS_EDEVICE",
+}
+
+
+class nps_dims(ctypes.Structure):
+    _fields_ = [("nz", ctypes.c_int), ("ny", ctypes.c_int), ("nx", ctypes.c_int)]
+
+
+class nps_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("n_ortho", ctypes.c_int),
+                ("precision", ctypes.c_int), ("refine_every", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+
+
+class nps_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
+                ("rel_residual_rec", ctypes.c_double), ("refinements", ctypes.c_int), ("n_fluid", ctypes.c_int)]
+
+
+class nps_kernel_stat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double),
+                ("cells", ctypes.c_double)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2310_00177_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _sz, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+
+_lib.nps_param_count.argtypes, _lib.nps_param_count.restype = [_int], _sz
+_lib.nps_net_bytes.argtypes, _lib.nps_net_bytes.restype = [_int], _sz
+_lib.nps_net_create.argtypes = [_vp, _sz, _int, _vp, _sz, _vp, ctypes.POINTER(_vp)]
+_lib.nps_net_create.restype = _int
+_lib.nps_net_destroy.argtypes, _lib.nps_net_destroy.restype = [_vp], None
+_lib.nps_net_levels.argtypes, _lib.nps_net_levels.restype = [_vp], _int
+_lib.nps_workspace_bytes.argtypes, _lib.nps_workspace_bytes.restype = [nps_dims, _int, _int, _int], _sz
+_lib.nps_solve.argtypes = [_vp, _vp, nps_dims, _vp, _vp, ctypes.POINTER(nps_opts), ctypes.POINTER(nps_info),
+                           _vp, _sz, _vp]
+_lib.nps_solve.restype = _int
+_lib.nps_apply_laplacian.argtypes = [_vp, nps_dims, _vp, _vp, _int, _vp]
+_lib.nps_apply_laplacian.restype = _int
+_lib.nps_apply_precond.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _int, _vp, _sz, _vp]
+_lib.nps_apply_precond.restype = _int
+_lib.nps_profile_enable.argtypes, _lib.nps_profile_enable.restype = [_int], _int
+_lib.nps_profile_read.argtypes = [ctypes.POINTER(nps_kernel_stat), _int, ctypes.POINTER(_int)]
+_lib.nps_profile_read.restype = _int
+_lib.nps_last_error.argtypes, _lib.nps_last_error.restype = [], ctypes.c_char_p
+
+EXPORTED = ["nps_param_count", "nps_net_bytes", "nps_net_create", "nps_net_destroy", "nps_net_levels",
+            "nps_workspace_bytes", "nps_solve", "nps_apply_laplacian", "nps_apply_precond", "nps_profile_enable",
+            "nps_profile_read", "nps_last_error"]
+
+
+def nps_param_count(levels: int) -> int:
+    return _lib.nps_param_count(levels)
+
+
+def nps_net_bytes(levels: int) -> int:
+    return _lib.nps_net_bytes(levels)
+
+
+def nps_net_create(params_h: int, n_params: int, levels: int, dev_buf_d: int, dev_bytes: int,
+                   stream: int) -> tuple:
+    """Returns (status, net handle)."""
+    out = _vp()
+    rc = _lib.nps_net_create(params_h, n_params, levels, dev_buf_d, dev_bytes, stream, ctypes.byref(out))
+    return rc, out.value
+
+
+def nps_net_destroy(net: int) -> None:
+    _lib.nps_net_destroy(net)
+
+
+def nps_net_levels(net: int) -> int:
+    return _lib.nps_net_levels(net)
+
+
+def nps_workspace_bytes(dims: nps_dims, levels: int, precision: int, n_ortho: int) -> int:
+    return _lib.nps_workspace_bytes(dims, levels, precision, n_ortho)
+
+
+def nps_solve(net: int, labels_d: int, dims: nps_dims, b_d: int, x_d: int, opts: nps_opts,
+              info: nps_info, ws_d: int, ws_bytes: int, stream: int) -> int:
+    return _lib.nps_solve(net, labels_d, dims, b_d, x_d, ctypes.byref(opts), ctypes.byref(info),
+                          ws_d, ws_bytes, stream)
+
+
+def nps_apply_laplacian(labels_d: int, dims: nps_dims, x_d: int, y_d: int, precision: int, stream: int) -> int:
+    return _lib.nps_apply_laplacian(labels_d, dims, x_d, y_d, precision, stream)
+
+
+def nps_apply_precond(net: int, labels_d: int, dims: nps_dims, r_d: int, d_d: int, precision: int,
+                      ws_d: int, ws_bytes: int, stream: int) -> int:
+    return _lib.nps_apply_precond(net, labels_d, dims, r_d, d_d, precision, ws_d, ws_bytes, stream)
+
+
+def nps_profile_enable(on: int) -> int:
+    return _lib.nps_profile_enable(on)
+
+
+def nps_profile_read(max_records: int = 64) -> tuple:
+    """Returns (status, [nps_kernel_stat, ...])."""
+    buf = (nps_kernel_stat * max_records)()
+    n = _int(0)
+    rc = _lib.nps_profile_read(buf, max_records, ctypes.byref(n))
+    return rc, [buf[i] for i in range(min(n.value, max_records))]
+
+
+def nps_last_error() -> str:
+    return _lib.nps_last_error().decode()

@@ -1,0 +1,828 @@
+// C-ABI of the neural-preconditioned Poisson solver (declared in include/nps.h).
+//
+// Host-side responsibilities: argument validation, conversion of the weight
+// blob into the count form and the MFMA operand layout the kernels use,
+// carving the caller's workspace, the per-solve setup (image pyramid, Aff
+// scalars, kernels of the small levels), and the Alg. 1 loop, which enqueues
+// one iteration's kernels at a time.  Convergence is decided on the device;
+// the host polls a copy of the device state one iteration behind, so the GPU
+// never waits for the host.
+#include "nps.h"
+#include "nps_internal.hpp"
+#include "nps_kernels.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+using namespace nps;
+
+struct nps_net {
+    int levels = 0;
+    char* dev = nullptr;
+    size_t off_w64 = 0, off_w32 = 0, off_mfma = 0, off_aff = 0;
+    double aff_b[2 * kMaxLevels] = {};   // Bbar of Aff_1^l, Aff_2^l (host copy)
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define NPS_HIP(call)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (call);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(NPS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+#define NPS_TRY(expr)            \
+    do {                         \
+        const int rc_ = (expr);  \
+        if (rc_) return rc_;     \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+Grid level_grid(nps_dims d, int level) {  // level 1 = finest
+    const int s = level - 1;
+    return Grid{d.nz >> s, d.ny >> s, d.nx >> s};
+}
+
+int check_dims(nps_dims d, int levels) {
+    if (levels < 2 || levels > kMaxLevels)
+        return fail(NPS_EINVAL, "levels must be in [2, %d], got %d", kMaxLevels, levels);
+    if (d.nz <= 0 || d.ny <= 0 || d.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    const int m = 1 << (levels - 1);
+    if (d.nz % m || d.ny % m || d.nx % m)
+        return fail(NPS_ESHAPE, "dims (%d,%d,%d) not divisible by 2^(levels-1) = %d", d.nz, d.ny, d.nx, m);
+    if ((double)d.nz * d.ny * d.nx > 1.0e9) return fail(NPS_ESHAPE, "grid too large");
+    return NPS_OK;
+}
+
+size_t vec_bytes(int precision) { return precision == NPS_FP64 ? 8 : 4; }
+size_t x_bytes(int precision) { return precision == NPS_FP32 ? 4 : 8; }
+
+// How each level evaluates its CConv blocks.
+struct Plan {
+    int L;
+    int lb;                      // first level run by the one-workgroup bottom kernel (L + 1: none)
+    int km[kMaxLevels + 2];      // KMode per level
+};
+
+Plan make_plan(nps_dims d, int levels, int precision) {
+    Plan p = {};
+    p.L = levels;
+    p.lb = levels + 1;
+    for (int l = 1; l <= levels; ++l) {
+        const size_t n = ncells(level_grid(d, l));
+        if (n <= (size_t)kStoreMaxCells) p.km[l] = kStored;
+        else if (precision == NPS_FP64 || l > kMfmaMaxLevel) p.km[l] = kVector;
+        else if (precision == NPS_FP32) p.km[l] = kMfmaBf16x3;
+        else if (precision == NPS_MIXED_BF16) p.km[l] = kMfmaBf16;
+        else p.km[l] = kMfmaF16;
+        if (l >= 2 && p.lb > levels && n <= (size_t)kBottomMaxCells) p.lb = l;
+    }
+    return p;
+}
+
+// Workspace carving, shared by nps_workspace_bytes, nps_solve and nps_apply_precond.
+struct Layout {
+    size_t state, partials;
+    size_t counts[kMaxLevels + 1];
+    size_t x1[kMaxLevels + 1];
+    size_t rb[kMaxLevels + 1];
+    size_t k1[kMaxLevels + 1], k2[kMaxLevels + 1];
+    size_t dhat, dring[kRing], adring[kRing], x[2], r;
+    size_t total;
+};
+
+Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solve) {
+    Layout L = {};
+    const Plan p = make_plan(d, levels, precision);
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    const size_t s = vec_bytes(precision);
+    const size_t n = ncells(level_grid(d, 1));
+    L.state = put(sizeof(State));
+    L.partials = put(sizeof(double) * kRedWidth * kMaxRedBlocks);
+    for (int l = 2; l <= levels; ++l) L.counts[l] = put(sizeof(uint32_t) * ncells(level_grid(d, l)));
+    for (int l = 1; l <= levels; ++l) L.x1[l] = put(s * ncells(level_grid(d, l)));
+    for (int l = 2; l <= levels; ++l) L.rb[l] = put(s * ncells(level_grid(d, l)));
+    for (int l = 1; l <= levels; ++l) {
+        if (p.km[l] != kStored) continue;
+        const size_t nl = ncells(level_grid(d, l));
+        L.k1[l] = put(s * kTaps * nl);
+        if (l < levels) L.k2[l] = put(s * kTaps * nl);
+    }
+    L.dhat = put(s * n);
+    if (solve) {
+        for (int i = 0; i <= n_ortho; ++i) {
+            L.dring[i] = put(s * n);
+            L.adring[i] = put(s * n);
+        }
+        L.x[0] = put(x_bytes(precision) * n);
+        L.x[1] = put(x_bytes(precision) * n);
+        L.r = put(s * n);
+    }
+    L.total = off;
+    return L;
+}
+
+int tile_grid(Grid g) { return std::max(1, tiles_of(g).count()); }
+int red_tile_grid(Grid g) { return red_blocks(tiles_of(g).count()); }
+int red_elem_grid(size_t n) { return red_blocks((int)std::min<size_t>((n + kBlock - 1) / kBlock, 1u << 30)); }
+int elem_grid(size_t n) { return (int)std::min<size_t>(std::max<size_t>((n + kBlock - 1) / kBlock, 1), 65536); }
+
+// Pinned host mirror of the device state, two slots for the one-behind poll.
+State* pinned_state() {
+    thread_local State* p = nullptr;
+    if (!p) {
+        if (hipHostMalloc((void**)&p, 2 * sizeof(State), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    }
+    return p;
+}
+
+// Optional per-kernel timing: an event pair around every launch.
+struct ProfRec {
+    const char* name;
+    int ev0, ev1;
+    double cells;
+};
+struct Prof {
+    bool on = false;
+    bool overflow = false;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;
+    std::vector<ProfRec> recs;
+};
+thread_local Prof g_prof;
+constexpr size_t kMaxProfEvents = 2000000;
+
+int prof_mark(hipStream_t s) {
+    Prof& p = g_prof;
+    if (p.next >= kMaxProfEvents) {
+        p.overflow = true;
+        return -1;
+    }
+    if (p.next == p.pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return -1;
+        p.pool.push_back(e);
+    }
+    if (hipEventRecord(p.pool[p.next], s) != hipSuccess) return -1;
+    return (int)p.next++;
+}
+
+// Launch through f(); checks the launch and records timing events if enabled.
+template <class F>
+int launch(const char* name, double cells, hipStream_t s, F&& f) {
+    int e0 = -1;
+    if (g_prof.on) e0 = prof_mark(s);
+    f();
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(NPS_EDEVICE, "launch of %s failed: %s", name, hipGetErrorString(e));
+    if (g_prof.on && e0 >= 0) {
+        const int e1 = prof_mark(s);
+        if (e1 >= 0) g_prof.recs.push_back(ProfRec{name, e0, e1, cells});
+    }
+    return NPS_OK;
+}
+
+size_t net_sizes(int levels, size_t* o64, size_t* o32, size_t* omf, size_t* oaff) {
+    const int nb = 2 * levels - 1;
+    size_t off = 0;
+    *o64 = off;
+    off += align256(sizeof(CConvW<double>) * nb);
+    *o32 = off;
+    off += align256(sizeof(CConvW<float>) * nb);
+    *omf = off;
+    off += align256(sizeof(MfmaW) * nb);
+    *oaff = off;
+    off += align256(sizeof(AffW) * 2 * (levels - 1));
+    return off;
+}
+
+// CConv block b: CConv_1^l is b = l - 1 (l = 1..L), CConv_2^l is b = L + l - 1.
+int block_down(int l) { return l - 1; }
+int block_up(const nps_net* net, int l) { return net->levels + l - 1; }
+
+template <class T>
+const CConvW<T>* cconv_block(const nps_net* net, int b) {
+    const size_t off = sizeof(T) == 8 ? net->off_w64 : net->off_w32;
+    return reinterpret_cast<const CConvW<T>*>(net->dev + off) + b;
+}
+const MfmaW* mfma_block(const nps_net* net, int b) {
+    return reinterpret_cast<const MfmaW*>(net->dev + net->off_mfma) + b;
+}
+const AffW* aff_block(const nps_net* net, int level, int which) {  // which: 0 -> Aff_1, 1 -> Aff_2
+    return reinterpret_cast<const AffW*>(net->dev + net->off_aff) + 2 * (level - 1) + which;
+}
+
+// Count form of one CConv block (see CConvW): double precision on the host.
+void to_count_form(const double* W, const double* B, int level, CConvW<double>& out) {
+    const double s = std::ldexp(1.0, -3 * (level - 1));   // 1 / 8^(l-1)
+    auto w = [&](int t, int c, int o) { return W[(t * 3 + c) * kTaps + o]; };
+    for (int t = 0; t < kTaps; ++t) {
+        double c = B[t];
+        for (int o = 0; o < kTaps; ++o) c += w(t, kSolid, o);
+        out.C[t] = c;
+        double kf = c, ka = c;
+        for (int o = 0; o < kTaps; ++o) {
+            const double d0 = w(t, kFluid, o) - w(t, kSolid, o);
+            const double d1 = w(t, kAir, o) - w(t, kSolid, o);
+            out.D[o][t][0] = d0 * s;
+            out.D[o][t][1] = d1 * s;
+            kf += d0;
+            ka += d1;
+        }
+        out.Kpure[kFluid][t] = kf;
+        out.Kpure[kAir][t] = ka;
+        out.Kpure[kSolid][t] = c;
+    }
+}
+
+uint16_t bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+uint16_t f16_rne(double v) {
+    const _Float16 h = (_Float16)(float)v;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+
+// The count-form block as the MFMA A operand, in per-lane order (see MfmaW).
+void to_mfma(const CConvW<double>& cw, MfmaW& m) {
+    for (int mb = 0; mb < 2; ++mb)
+        for (int ks = 0; ks < 2; ++ks)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int i = 0; i < 8; ++i) {
+                    const int tap = 16 * mb + lane % 16, k = 32 * ks + 8 * (lane / 16) + i;
+                    double v = 0.0;
+                    if (tap < kTaps) {
+                        if (k < 2 * kTaps) v = cw.D[k / 2][tap][k % 2];
+                        else if (k == 2 * kTaps) v = cw.C[tap];
+                    }
+                    double rest = v;
+                    for (int p = 0; p < kPieces; ++p) {
+                        const uint16_t h = bf16_rne((float)rest);
+                        m.bf16[p][mb][ks][lane][i] = h;
+                        rest -= bf16_value(h);
+                    }
+                    m.f16[mb][ks][lane][i] = f16_rne(v);
+                }
+}
+
+template <class T>
+const T* cptr(void* ws, size_t off) {
+    return reinterpret_cast<const T*>(static_cast<char*>(ws) + off);
+}
+template <class T>
+T* mptr(void* ws, size_t off) {
+    return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+uint32_t full_count(int l) { return 1u << (3 * (l - 1)); }
+
+// Image pyramid as counts, Aff scalars, and the stored kernels of small levels.
+template <class T>
+int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay,
+              void* ws, hipStream_t s) {
+    const int L = net->levels;
+    State* st = mptr<State>(ws, lay.state);
+    double* partials = mptr<double>(ws, lay.partials);
+    for (int l = 2; l <= L; ++l) {
+        const Grid gin = level_grid(d, l - 1), gout = level_grid(d, l);
+        uint32_t* out = mptr<uint32_t>(ws, lay.counts[l]);
+        const int grid = elem_grid(ncells(gout));
+        if (l == 2)
+            NPS_TRY(launch("setup_pool_counts", (double)ncells(gout), s, [&] {
+                k_pool_counts<true><<<grid, kBlock, 0, s>>>(labels, gin, out, gout);
+            }));
+        else
+            NPS_TRY(launch("setup_pool_counts", (double)ncells(gout), s, [&] {
+                k_pool_counts<false><<<grid, kBlock, 0, s>>>(cptr<uint32_t>(ws, lay.counts[l - 1]), gin, out, gout);
+            }));
+    }
+    auto img = [&](int l) -> const void* {
+        return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
+    };
+    for (int l = 1; l < L; ++l) {
+        const Grid g = level_grid(d, l);
+        const double inv_full = std::ldexp(1.0, -3 * (l - 1));
+        const int grid = red_elem_grid(ncells(g));
+        if (l == 1)
+            NPS_TRY(launch("setup_aff", (double)ncells(g), s, [&] {
+                k_aff<true><<<grid, kBlock, 0, s>>>(img(l), g, inv_full, aff_block(net, l, 0), aff_block(net, l, 1), partials);
+            }));
+        else
+            NPS_TRY(launch("setup_aff", (double)ncells(g), s, [&] {
+                k_aff<false><<<grid, kBlock, 0, s>>>(img(l), g, inv_full, aff_block(net, l, 0), aff_block(net, l, 1), partials);
+            }));
+        const double b1 = net->aff_b[2 * (l - 1)], b2 = net->aff_b[2 * (l - 1) + 1];
+        NPS_TRY(launch("control", 0, s, [&] {
+            k_control<kStageAff><<<1, kCtlBlock, 0, s>>>(st, partials, grid, l - 1, 0, 0, 0, b1, b2, 27.0 * (double)ncells(g));
+        }));
+    }
+    for (int l = 1; l <= L; ++l) {
+        if (plan.km[l] != kStored) continue;
+        const Grid g = level_grid(d, l);
+        const int grid = elem_grid(ncells(g));
+        for (int which = 0; which < (l < L ? 2 : 1); ++which) {
+            T* out = mptr<T>(ws, which == 0 ? lay.k1[l] : lay.k2[l]);
+            const CConvW<double>* w = cconv_block<double>(net, which == 0 ? block_down(l) : block_up(net, l));
+            if (l == 1)
+                NPS_TRY(launch("setup_kgen", (double)ncells(g), s, [&] { k_kgen_store<T, true><<<grid, kBlock, 0, s>>>(img(l), g, w, out); }));
+            else
+                NPS_TRY(launch("setup_kgen", (double)ncells(g), s, [&] { k_kgen_store<T, false><<<grid, kBlock, 0, s>>>(img(l), g, w, out); }));
+        }
+    }
+    return NPS_OK;
+}
+
+// Kernel dispatch over the per-level KMode (MFMA modes exist for float only).
+template <class T, class F>
+int with_kmode(int km, F&& f) {
+    switch (km) {
+        case kVector: return f(std::integral_constant<int, kVector>());
+        case kStored: return f(std::integral_constant<int, kStored>());
+        default: break;
+    }
+    if constexpr (std::is_same_v<T, float>) {
+        switch (km) {
+            case kMfmaBf16x3: return f(std::integral_constant<int, kMfmaBf16x3>());
+            case kMfmaBf16: return f(std::integral_constant<int, kMfmaBf16>());
+            case kMfmaF16: return f(std::integral_constant<int, kMfmaF16>());
+            default: break;
+        }
+    }
+    return fail(NPS_EINVAL, "kernel mode %d not available for this precision", km);
+}
+
+// Alg. 2 below level 1: coarse down levels, bottom workgroup, coarse up
+// levels.  On return *x2 points at x^2, the input of level 1's up block.
+template <class T>
+int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& lay, void* ws, hipStream_t s,
+               const T** x2) {
+    const int L = net->levels;
+    State* st = mptr<State>(ws, lay.state);
+    const int last_down = std::min(plan.lb - 1, L);   // levels handled by k_down
+    for (int l = 2; l <= last_down; ++l) {
+        const Grid g = level_grid(d, l);
+        const uint32_t* cnt = cptr<uint32_t>(ws, lay.counts[l]);
+        const T* rin = cptr<T>(ws, lay.rb[l]);
+        T* x1 = mptr<T>(ws, lay.x1[l]);
+        T* rnext = l < L ? mptr<T>(ws, lay.rb[l + 1]) : nullptr;
+        const CConvW<T>* w = cconv_block<T>(net, block_down(l));
+        const MfmaW* wm = mfma_block(net, block_down(l));
+        const T* kst = plan.km[l] == kStored ? cptr<T>(ws, lay.k1[l]) : nullptr;
+        const int grid = tile_grid(g);
+        const double cells = (double)ncells(g);
+        NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
+            constexpr int KM = decltype(km)::value;
+            if (l < L)
+                return launch("net_down", cells, s, [&] {
+                    k_down<T, KM, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, wm, kst, st);
+                });
+            return launch("net_coarsest", cells, s, [&] {
+                k_down<T, KM, false><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, nullptr, w, wm, kst, st);
+            });
+        }));
+    }
+    if (plan.lb <= L) {
+        BottomArgs<T> a = {};
+        a.lb = plan.lb;
+        a.L = L;
+        size_t cells = 0;
+        for (int l = plan.lb; l <= L; ++l) {
+            a.g[l] = level_grid(d, l);
+            a.k1[l] = cptr<T>(ws, lay.k1[l]);
+            a.k2[l] = l < L ? cptr<T>(ws, lay.k2[l]) : nullptr;
+            cells += ncells(a.g[l]);
+        }
+        if (2 * cells > (size_t)kBottomLds) return fail(NPS_EINVAL, "bottom levels exceed the workgroup buffer");
+        a.rin = cptr<T>(ws, lay.rb[plan.lb]);
+        a.xout = mptr<T>(ws, lay.rb[plan.lb]);
+        NPS_TRY(launch("net_bottom", (double)cells, s, [&] { k_bottom<T><<<1, kBottomThreads, 0, s>>>(a, st); }));
+    }
+    auto x_of = [&](int l) -> const T* {   // x^l, the up-sweep output of level l
+        return (l == L && plan.lb > L) ? cptr<T>(ws, lay.x1[L]) : cptr<T>(ws, lay.rb[l]);
+    };
+    const int first_up = std::min(plan.lb - 1, L - 1);
+    for (int l = first_up; l >= 2; --l) {
+        const Grid g = level_grid(d, l);
+        const uint32_t* cnt = cptr<uint32_t>(ws, lay.counts[l]);
+        const T* xc = x_of(l + 1);
+        const T* x1 = cptr<T>(ws, lay.x1[l]);
+        T* xo = mptr<T>(ws, lay.rb[l]);
+        const CConvW<T>* w = cconv_block<T>(net, block_up(net, l));
+        const MfmaW* wm = mfma_block(net, block_up(net, l));
+        const T* kst = plan.km[l] == kStored ? cptr<T>(ws, lay.k2[l]) : nullptr;
+        const int grid = tile_grid(g);
+        NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
+            constexpr int KM = decltype(km)::value;
+            return launch("net_up", (double)ncells(g), s, [&] {
+                k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st);
+            });
+        }));
+    }
+    *x2 = x_of(2);
+    return NPS_OK;
+}
+
+// Level-1 down kernel.  HOOK: network only (r is the input).
+template <class T, class X, bool HOOK>
+int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
+                const double* b, X* xb0, X* xb1, const T* dpend, T* r, hipStream_t s) {
+    const Grid g = level_grid(d, 1);
+    State* st = mptr<State>(ws, lay.state);
+    double* partials = mptr<double>(ws, lay.partials);
+    T* x1 = mptr<T>(ws, lay.x1[1]);
+    T* rnext = mptr<T>(ws, lay.rb[2]);
+    const CConvW<T>* w = cconv_block<T>(net, block_down(1));
+    const MfmaW* wm = mfma_block(net, block_down(1));
+    const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k1[1]) : nullptr;
+    const int grid = HOOK ? tile_grid(g) : red_tile_grid(g);
+    return with_kmode<T>(plan.km[1], [&](auto km) {
+        constexpr int KM = decltype(km)::value;
+        return launch("net_down_l1", (double)ncells(g), s, [&] {
+            k_down_l1<T, X, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, b, xb0, xb1, dpend, r, x1, rnext, w, wm, kst, st,
+                                                              partials);
+        });
+    });
+}
+
+// Level-1 up kernel; *nparts receives its grid (the number of partials).
+template <class T, bool HOOK>
+int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
+              const T* x2, T* dhat, const T* const* ad, hipStream_t s, int* nparts) {
+    const Grid g = level_grid(d, 1);
+    State* st = mptr<State>(ws, lay.state);
+    double* partials = mptr<double>(ws, lay.partials);
+    const T* x1 = cptr<T>(ws, lay.x1[1]);
+    const CConvW<T>* w = cconv_block<T>(net, block_up(net, 1));
+    const MfmaW* wm = mfma_block(net, block_up(net, 1));
+    const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k2[1]) : nullptr;
+    const int grid = HOOK ? tile_grid(g) : red_tile_grid(g);
+    if (nparts) *nparts = grid;
+    return with_kmode<T>(plan.km[1], [&](auto km) {
+        constexpr int KM = decltype(km)::value;
+        return launch("net_up_l1", (double)ncells(g), s, [&] {
+            k_up_l1<T, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, kst, st, partials, ad[0], ad[1],
+                                                        ad[2], ad[3]);
+        });
+    });
+}
+
+template <class T, class X>
+int solve_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const double* b, double* x_out,
+               const nps_opts& o, nps_info* info, void* ws, const Plan& plan, const Layout& lay, hipStream_t s) {
+    const Grid g = level_grid(d, 1);
+    const size_t n = ncells(g);
+    State* st = mptr<State>(ws, lay.state);
+    double* partials = mptr<double>(ws, lay.partials);
+    X* x = mptr<X>(ws, lay.x[0]);
+    X* xb1 = mptr<X>(ws, lay.x[1]);
+    T* r = mptr<T>(ws, lay.r);
+    T* dhat = mptr<T>(ws, lay.dhat);
+    const int max_iter = std::max(o.max_iter, 0);
+    State* hs = pinned_state();
+    if (!hs) return fail(NPS_EDEVICE, "hipHostMalloc of the state mirror failed");
+    const double cells = (double)n;
+
+    NPS_TRY(launch("state_init", 0, s, [&] {
+        k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho);
+    }));
+    const int sgrid = red_elem_grid(n);
+    NPS_TRY(launch("setup_scan", cells, s, [&] { k_scan<X><<<sgrid, kBlock, 0, s>>>(labels, b, n, x, partials); }));
+    NPS_TRY(launch("control", 0, s, [&] {
+        k_control<kStageScan><<<1, kCtlBlock, 0, s>>>(st, partials, sgrid, 0, 0, 0, 0, o.tol, 0.0, 0.0);
+    }));
+    NPS_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipStreamSynchronize(s));
+    if (hs->bad_label) return fail(NPS_ELABEL, "%d labels outside {0,1,2}", hs->bad_label);
+    if (hs->n_fluid == 0) return fail(NPS_ENOFLUID, "no fluid cell");
+    if (hs->nonfinite) return fail(NPS_ENONFINITE, "%d non-finite entries of b on fluid cells", hs->nonfinite);
+    info->n_fluid = hs->n_fluid;
+    const double bb = hs->bb;
+    if (bb == 0.0) {   // x = 0 solves it exactly
+        NPS_TRY(launch("finalize", cells, s, [&] {
+            k_finalize<X><<<elem_grid(n), kBlock, 0, s>>>(n, labels, x, xb1, st, x_out);
+        }));
+        NPS_HIP(hipStreamSynchronize(s));
+        info->status = NPS_OK;
+        return NPS_OK;
+    }
+    NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
+
+    const int R = o.n_ortho + 1;
+    const int rgrid = red_tile_grid(g);
+    hipEvent_t ev[2];
+    NPS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    NPS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    int result = NPS_OK;
+    // Body k forms x_(k-1) and r_(k-1), then the direction d_k and its step.
+    for (int k = 1; k <= max_iter + 1 && result == NPS_OK; ++k) {
+        const int slot = k % R;
+        const T* ad[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
+        const T* dp[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
+        int sl[kMaxOrtho] = {0, 0, 0, 0};
+        for (int j = 0; j < o.n_ortho; ++j) {
+            sl[j] = ((k - 1 - j) % R + R) % R;
+            dp[j] = cptr<T>(ws, lay.dring[sl[j]]);
+            ad[j] = cptr<T>(ws, lay.adring[sl[j]]);
+        }
+        const T* dpend = cptr<T>(ws, lay.dring[((k - 1) % R + R) % R]);
+        T* dk = mptr<T>(ws, lay.dring[slot]);
+        T* adk = mptr<T>(ws, lay.adring[slot]);
+        const T* x2 = nullptr;
+        int np = 0;
+        int rc = run_down_l1<T, X, false>(net, labels, d, plan, lay, ws, b, x, xb1, dpend, r, s);
+        if (!rc) rc = launch("control", 0, s, [&] {
+            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, 0, 0, 0, 0, 0.0, 0.0, 0.0);
+        });
+        if (!rc) rc = run_coarse<T>(net, d, plan, lay, ws, s, &x2);
+        if (!rc) rc = run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np);
+        if (!rc && o.n_ortho > 0) rc = launch("control", 0, s, [&] {
+            k_control<kStageDots><<<1, kCtlBlock, 0, s>>>(st, partials, np, sl[0], sl[1], sl[2], sl[3], 0.0, 0.0, 0.0);
+        });
+        if (!rc) rc = launch("ortho_matvec", cells, s, [&] {
+            k_ortho<T><<<rgrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r, dk, adk, st, partials);
+        });
+        if (!rc) rc = launch("control", 0, s, [&] {
+            k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, slot, 0, 0, 0, 0.0, 0.0, 0.0);
+        });
+        if (rc) {
+            result = rc;
+            break;
+        }
+        NPS_HIP(hipMemcpyAsync(&hs[k & 1], st, sizeof(State), hipMemcpyDeviceToHost, s));
+        NPS_HIP(hipEventRecord(ev[k & 1], s));
+        if (k >= 2) {
+            NPS_HIP(hipEventSynchronize(ev[(k - 1) & 1]));
+            if (hs[(k - 1) & 1].done) break;
+        }
+    }
+    if (result == NPS_OK) {
+        result = launch("finalize", cells, s, [&] {
+            k_finalize<X><<<elem_grid(n), kBlock, 0, s>>>(n, labels, x, xb1, st, x_out);
+        });
+    }
+    if (result == NPS_OK) {
+        NPS_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+        NPS_HIP(hipStreamSynchronize(s));
+        info->iterations = hs->iter;
+        info->status = hs->done ? hs->status : NPS_NOT_CONVERGED;
+        info->rel_residual = std::sqrt(hs->rr / bb);
+        info->rel_residual_rec = info->rel_residual;
+        info->refinements = hs->iter + 1;
+        result = info->status;
+        if (result == NPS_EBREAKDOWN)
+            fail(NPS_EBREAKDOWN, "breakdown: d.Ad <= 0 or not finite at iteration %d", hs->iter + 1);
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    return result;
+}
+
+template <class T>
+int precond_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const T* r_in, T* d_out, void* ws,
+                 const Plan& plan, const Layout& lay, hipStream_t s) {
+    State* st = mptr<State>(ws, lay.state);
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0); }));
+    NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
+    NPS_TRY((run_down_l1<T, T, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr,
+                                     const_cast<T*>(r_in), s)));
+    const T* x2 = nullptr;
+    NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
+    const T* none[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
+    return run_up_l1<T, true>(net, labels, d, plan, lay, ws, x2, d_out, none, s, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t nps_param_count(int levels) {
+    if (levels < 1) return 0;
+    return (size_t)(2 * levels - 1) * (27 * 81 + 27) + (size_t)2 * (levels - 1) * (81 + 1);
+}
+
+size_t nps_net_bytes(int levels) {
+    if (levels < 2 || levels > kMaxLevels) return 0;
+    size_t a, b, c, e;
+    return net_sizes(levels, &a, &b, &c, &e);
+}
+
+int nps_net_levels(const nps_net* net) { return net ? net->levels : 0; }
+
+int nps_net_create(const double* params_h, size_t n_params, int levels, void* dev_buf_d, size_t dev_bytes,
+                   void* stream, nps_net** out) {
+    if (!params_h || !dev_buf_d || !out) return fail(NPS_EINVAL, "null argument");
+    if (levels < 2 || levels > kMaxLevels) return fail(NPS_EINVAL, "levels must be in [2, %d]", kMaxLevels);
+    if (n_params != nps_param_count(levels))
+        return fail(NPS_EINVAL, "blob has %zu parameters, expected %zu", n_params, nps_param_count(levels));
+    if (reinterpret_cast<uintptr_t>(dev_buf_d) % 256) return fail(NPS_EINVAL, "device buffer not 256-byte aligned");
+    size_t o64, o32, omf, oaff;
+    const size_t need = net_sizes(levels, &o64, &o32, &omf, &oaff);
+    if (dev_bytes < need) return fail(NPS_ENOMEM, "device buffer has %zu bytes, needs %zu", dev_bytes, need);
+    for (size_t i = 0; i < n_params; ++i)
+        if (!std::isfinite(params_h[i])) return fail(NPS_ENONFINITE, "parameter %zu is not finite", i);
+
+    std::vector<char> host(need, 0);
+    const int nb = 2 * levels - 1;
+    auto* w64 = reinterpret_cast<CConvW<double>*>(host.data() + o64);
+    auto* w32 = reinterpret_cast<CConvW<float>*>(host.data() + o32);
+    auto* wmf = reinterpret_cast<MfmaW*>(host.data() + omf);
+    auto* aff = reinterpret_cast<AffW*>(host.data() + oaff);
+    nps_net* net = new nps_net();
+    const double* p = params_h;
+    const size_t cw = 27 * 81, cb = 27;
+    for (int l = 1; l <= levels; ++l) {              // CConv_1^l
+        to_count_form(p, p + cw, l, w64[l - 1]);
+        p += cw + cb;
+    }
+    for (int l = 1; l < levels; ++l) {               // CConv_2^l
+        to_count_form(p, p + cw, l, w64[levels + l - 1]);
+        p += cw + cb;
+    }
+    for (int l = 1; l < levels; ++l) {               // Aff_1^l, Aff_2^l
+        for (int which = 0; which < 2; ++which) {
+            AffW& a = aff[2 * (l - 1) + which];
+            for (int c = 0; c < 3; ++c)
+                for (int o = 0; o < kTaps; ++o) a.w[c][o] = p[c * kTaps + o];
+            a.b = p[81];
+            net->aff_b[2 * (l - 1) + which] = p[81];
+            p += 82;
+        }
+    }
+    for (int b = 0; b < nb; ++b) {
+        const CConvW<double>& s = w64[b];
+        CConvW<float>& t = w32[b];
+        for (int i = 0; i < kTaps; ++i) t.C[i] = (float)s.C[i];
+        for (int o = 0; o < kTaps; ++o)
+            for (int i = 0; i < kTaps; ++i)
+                for (int c = 0; c < 2; ++c) t.D[o][i][c] = (float)s.D[o][i][c];
+        for (int c = 0; c < 3; ++c)
+            for (int i = 0; i < kTaps; ++i) t.Kpure[c][i] = (float)s.Kpure[c][i];
+        to_mfma(s, wmf[b]);
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(dev_buf_d, host.data(), need, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete net;
+        return fail(NPS_EDEVICE, "copy of the network to the device failed: %s", hipGetErrorString(e));
+    }
+    net->levels = levels;
+    net->dev = static_cast<char*>(dev_buf_d);
+    net->off_w64 = o64;
+    net->off_w32 = o32;
+    net->off_mfma = omf;
+    net->off_aff = oaff;
+    *out = net;
+    return NPS_OK;
+}
+
+void nps_net_destroy(nps_net* net) { delete net; }
+
+size_t nps_workspace_bytes(nps_dims dims, int levels, int precision, int n_ortho) {
+    if (check_dims(dims, levels) != NPS_OK) return 0;
+    if (precision < NPS_FP64 || precision > NPS_MIXED_FP16) return 0;
+    if (n_ortho < 0 || n_ortho > kMaxOrtho) return 0;
+    return make_layout(dims, levels, precision, n_ortho, true).total;
+}
+
+int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const double* b_d, double* x_d,
+              const nps_opts* opts, nps_info* info, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!net || !labels_d || !b_d || !x_d || !opts || !info || !ws_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    const nps_opts& o = *opts;
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NPS_EINVAL, "tol must be positive and finite");
+    if (o.max_iter < 0) return fail(NPS_EINVAL, "max_iter must be >= 0");
+    if (o.n_ortho < 0 || o.n_ortho > kMaxOrtho) return fail(NPS_EINVAL, "n_ortho must be in [0, %d]", kMaxOrtho);
+    if (o.precision < NPS_FP64 || o.precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", o.precision);
+    const Plan plan = make_plan(dims, net->levels, o.precision);
+    const Layout lay = make_layout(dims, net->levels, o.precision, o.n_ortho, true);
+    if (ws_bytes < lay.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    std::memset(info, 0, sizeof(*info));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    switch (o.precision) {
+        case NPS_FP64: return solve_impl<double, double>(net, labels_d, dims, b_d, x_d, o, info, ws_d, plan, lay, s);
+        case NPS_FP32: return solve_impl<float, float>(net, labels_d, dims, b_d, x_d, o, info, ws_d, plan, lay, s);
+        default: return solve_impl<float, double>(net, labels_d, dims, b_d, x_d, o, info, ws_d, plan, lay, s);
+    }
+}
+
+int nps_apply_laplacian(const uint8_t* labels_d, nps_dims dims, const void* x_d, void* y_d, int precision,
+                        void* stream) {
+    if (!labels_d || !x_d || !y_d) return fail(NPS_EINVAL, "null argument");
+    if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Grid g{dims.nz, dims.ny, dims.nx};
+    const int grid = std::min(tile_grid(g), 65536);
+    const double cells = (double)ncells(g);
+    if (precision == NPS_FP64)
+        return launch("laplacian", cells, s, [&] {
+            k_laplacian<double><<<grid, kBlock, 0, s>>>(labels_d, g, static_cast<const double*>(x_d),
+                                                        static_cast<double*>(y_d));
+        });
+    if (precision == NPS_FP32)
+        return launch("laplacian", cells, s, [&] {
+            k_laplacian<float><<<grid, kBlock, 0, s>>>(labels_d, g, static_cast<const float*>(x_d),
+                                                       static_cast<float*>(y_d));
+        });
+    return fail(NPS_EINVAL, "precision must be NPS_FP64 or NPS_FP32");
+}
+
+int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, void* d_d,
+                      int precision, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!net || !labels_d || !r_d || !d_d || !ws_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (precision < NPS_FP64 || precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", precision);
+    const Plan plan = make_plan(dims, net->levels, precision);
+    const Layout lay = make_layout(dims, net->levels, precision, 0, false);
+    if (ws_bytes < lay.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == NPS_FP64)
+        return precond_impl<double>(net, labels_d, dims, static_cast<const double*>(r_d), static_cast<double*>(d_d),
+                                    ws_d, plan, lay, s);
+    return precond_impl<float>(net, labels_d, dims, static_cast<const float*>(r_d), static_cast<float*>(d_d), ws_d,
+                               plan, lay, s);
+}
+
+int nps_profile_enable(int on) {
+    g_prof.on = on != 0;
+    return NPS_OK;
+}
+
+int nps_profile_read(nps_kernel_stat* out_h, int max_records, int* n_records) {
+    if (!n_records || (max_records > 0 && !out_h)) return fail(NPS_EINVAL, "null argument");
+    Prof& p = g_prof;
+    std::vector<nps_kernel_stat> agg;
+    int rc = NPS_OK;
+    if (!p.recs.empty()) {
+        if (hipEventSynchronize(p.pool[p.recs.back().ev1]) != hipSuccess) rc = fail(NPS_EDEVICE, "event sync failed");
+    }
+    for (const ProfRec& r : p.recs) {
+        if (rc) break;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.pool[r.ev0], p.pool[r.ev1]) != hipSuccess) {
+            rc = fail(NPS_EDEVICE, "hipEventElapsedTime failed");
+            break;
+        }
+        auto it = std::find_if(agg.begin(), agg.end(), [&](const nps_kernel_stat& k) { return !std::strcmp(k.name, r.name); });
+        if (it == agg.end()) {
+            nps_kernel_stat k = {};
+            std::snprintf(k.name, sizeof k.name, "%s", r.name);
+            agg.push_back(k);
+            it = agg.end() - 1;
+        }
+        it->launches += 1;
+        it->total_ms += ms;
+        it->cells += r.cells;
+    }
+    const bool overflow = p.overflow;
+    p.recs.clear();
+    p.next = 0;
+    p.overflow = false;
+    *n_records = (int)agg.size();
+    for (int i = 0; i < (int)agg.size() && i < max_records; ++i) out_h[i] = agg[i];
+    if (rc) return rc;
+    if (overflow) return fail(NPS_ENOMEM, "more than %zu timing events; later launches were not recorded", kMaxProfEvents / 2);
+    return NPS_OK;
+}
+
+const char* nps_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,945 @@
+// HIP kernels for gfx950 (CDNA4) of the neural-preconditioned Poisson solve.
+//
+// One NPSDO iteration (Alg. 1) is a fixed sequence of launches:
+//   down_l1     x_k = x_(k-1) + alpha_k d_k, the literal residual r_k = b - A x_k,
+//               CConv_1^1(r_k) and its 2x average pool; partial ||r_k||^2
+//   control     ||r_k||, convergence, iteration count
+//   down/up     Alg. 2 on the coarser levels (CConv_1 + pool down; trilinear
+//               upsampling + CConv_2 + c1 x1 + c2 x2 up), the smallest levels
+//               in one workgroup ("bottom")
+//   up_l1       dhat = P(r)/||r|| on fluid cells; partial dhat . A d_i
+//   control     beta_i = dhat . A d_i / d_i . A d_i
+//   ortho       d = dhat - sum beta_i d_i, A d; partial d . A d, r . d
+//   control     alpha = r . d / d . A d, breakdown test
+// The per-cell kernels K_t(p) of a level are either regenerated from the
+// labels on chip every application (MFMA for the large levels, vector ALU in
+// FP64) or, for levels of at most 32768 cells, formed once per solve.
+//
+// No kernel synchronises across workgroups: each reduction writes one
+// partial per block, and the one-block control kernel that follows sums them
+// in block order (deterministic) and updates the solver state.  Kernel
+// boundaries provide the cross-XCD visibility.
+#include "nps_internal.hpp"
+
+#include <cmath>
+
+namespace nps {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block sum of kRedWidth values, written by thread 0 to partials[blockIdx.x].
+template <int NT>
+__device__ inline void block_partials(double (&v)[kRedWidth], double* partials) {
+    __shared__ double sh[kRedWidth][NT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int w = 0; w < kRedWidth; ++w) v[w] = wave_sum(v[w]);
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < kRedWidth; ++w) sh[w][wid] = v[w];
+    }
+    __syncthreads();
+    if (threadIdx.x < kRedWidth) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += sh[threadIdx.x][i];
+        partials[(size_t)blockIdx.x * kRedWidth + threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// tile helpers
+// ---------------------------------------------------------------------------
+struct TileOrigin {
+    int x0, y0, z0;
+};
+
+__device__ inline TileOrigin tile_origin(int tile, Tiles tl) {
+    TileOrigin o;
+    o.x0 = (tile % tl.ntx) * TX;
+    o.y0 = ((tile / tl.ntx) % tl.nty) * TY;
+    o.z0 = (tile / (tl.ntx * tl.nty)) * TZ;
+    return o;
+}
+
+__device__ inline size_t cell_index(Grid g, int z, int y, int x) {
+    return ((size_t)z * g.ny + y) * g.nx + x;
+}
+
+__device__ inline bool in_grid(Grid g, int z, int y, int x) {
+    return x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz;
+}
+
+// Offset of window position o = 9(oz+1) + 3(oy+1) + (ox+1) inside the haloed LDS tile.
+__host__ __device__ constexpr int halo_off(int o) {
+    return (o / 9 - 1) * HY * HX + ((o / 3) % 3 - 1) * HX + (o % 3 - 1);
+}
+
+__device__ inline int halo_base(int lx, int ly, int lz) { return ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1); }
+
+// Stage the image of a level over the haloed tile.  Level 1: labels (out of
+// grid -> solid).  Coarser levels: packed counts n_fluid | n_air << 16 (out
+// of grid -> 0, i.e. solid).
+template <bool L1>
+__device__ inline void stage_image(uint32_t* img_s, const void* img, Grid g, TileOrigin o) {
+    for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        const int x = o.x0 + hx - 1, y = o.y0 + hy - 1, z = o.z0 + hz - 1;
+        const bool in = in_grid(g, z, y, x);
+        uint32_t v;
+        if (L1) v = in ? (uint32_t)static_cast<const uint8_t*>(img)[cell_index(g, z, y, x)] : (uint32_t)kSolid;
+        else v = in ? static_cast<const uint32_t*>(img)[cell_index(g, z, y, x)] : 0u;
+        img_s[i] = v;
+    }
+}
+
+template <bool L1>
+__device__ inline void counts_of(uint32_t v, uint32_t& n0, uint32_t& n1) {
+    if (L1) {
+        n0 = v == kFluid;
+        n1 = v == kAir;
+    } else {
+        n0 = v & 0xffffu;
+        n1 = v >> 16;
+    }
+}
+
+// Window class of the cell at `base`: pure label c (0..2) when all 27 window
+// cells are pure cells of label c, else -1.  any_fluid: a window cell holds fluid.
+template <bool L1>
+__device__ inline int window_class(const uint32_t* img_s, int base, uint32_t full, bool& any_fluid) {
+    int cls = -2;
+    bool mixed = false;
+    any_fluid = false;
+#pragma unroll
+    for (int o = 0; o < kTaps; ++o) {
+        const uint32_t v = img_s[base + halo_off(o)];
+        int c;
+        if (L1) {
+            c = (int)v;
+            any_fluid |= (v == kFluid);
+        } else {
+            const uint32_t n0 = v & 0xffffu, n1 = v >> 16;
+            any_fluid |= (n0 != 0u);
+            c = n0 == full ? 0 : (n1 == full ? 1 : ((n0 | n1) == 0u ? 2 : -1));
+        }
+        mixed |= (c < 0) || (cls >= 0 && c != cls);
+        cls = c;
+    }
+    return mixed ? -1 : cls;
+}
+
+// Wave-uniform choice of the CConv path: -3 every output of the wave is
+// zero, 0..2 every window of the wave is pure label c (constant kernel),
+// -1 general.
+template <bool L1>
+__device__ inline int choose_mode(bool active, const uint32_t* img_s, int base, uint32_t full,
+                                  bool zero_if_no_fluid, bool out_only_on_fluid) {
+    bool any_fluid = false;
+    int cls = -1;
+    bool own_fluid = false;
+    if (active) {
+        cls = window_class<L1>(img_s, base, full, any_fluid);
+        own_fluid = img_s[base] == (uint32_t)kFluid;
+    }
+    if (zero_if_no_fluid && __all(!active || !any_fluid)) return -3;
+    if (out_only_on_fluid && __all(!active || !own_fluid)) return -3;
+    const int c0 = __shfl(cls, 0, 64);
+    if (__all(active && cls == c0 && cls >= 0)) return c0;
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// CConv evaluation of one output cell, per kernel-generation mode
+// ---------------------------------------------------------------------------
+// Vector ALU: K from the count form, then the 27-tap apply.
+template <class T, bool L1>
+__device__ inline T cconv_vector(const uint32_t* img_s, const T* r_s, int base, const CConvW<T>* __restrict__ w) {
+    T K[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) K[t] = w->C[t];
+#pragma unroll
+    for (int o = 0; o < kTaps; ++o) {
+        uint32_t c0, c1;
+        counts_of<L1>(img_s[base + halo_off(o)], c0, c1);
+        const T n0 = (T)c0, n1 = (T)c1;
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) K[t] = fma(w->D[o][t][0], n0, fma(w->D[o][t][1], n1, K[t]));
+    }
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc = fma(K[t], r_s[base + halo_off(t)], acc);
+    return acc;
+}
+
+template <class T>
+__device__ inline T cconv_pure(const T* r_s, int base, const CConvW<T>* __restrict__ w, int c) {
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc = fma(w->Kpure[c][t], r_s[base + halo_off(t)], acc);
+    return acc;
+}
+
+// Stored kernels: K[t][cell] formed at setup.
+template <class T>
+__device__ inline T cconv_stored(const T* r_s, int base, const T* __restrict__ kst, size_t n, size_t idx) {
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc = fma(kst[(size_t)t * n + idx], r_s[base + halo_off(t)], acc);
+    return acc;
+}
+
+__device__ inline int halo_off_rt(int o) {   // runtime version of halo_off
+    const int oz = o / 9, oy = (o / 3) - 3 * oz, ox = o - 3 * (o / 3);
+    return (oz - 1) * HY * HX + (oy - 1) * HX + (ox - 1);
+}
+
+// MFMA: one wave evaluates the CConv of its 64 cells (one z-plane of the
+// tile, x = lane % 16, y = lane / 16) as four 16-cell groups.  For group q
+// (y = q) the kernels of the 16 cells are K^T[tap][cell] = A[tap][feature] x
+// B[feature][cell] on v_mfma_f32_16x16x32 (2 tap blocks x 2 feature steps,
+// times the bf16 pieces); each lane then applies its 8 taps of one cell and
+// the four lane groups are summed with two butterflies.  Returns the output
+// of the lane's own cell.  All 64 lanes must call it.
+template <int KM, bool L1>
+__device__ inline float cconv_mfma(const uint32_t* img_s, const float* r_s, int lz, const MfmaW* __restrict__ wm) {
+    constexpr int P = KM == kMfmaBf16x3 ? kPieces : 1;
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+    u16x8 A[P][2][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) {
+                const uint16_t* src = KM == kMfmaF16 ? &wm->f16[mb][ks][lane][0] : &wm->bf16[p][mb][ks][lane][0];
+                A[p][mb][ks] = *reinterpret_cast<const u16x8*>(src);
+            }
+    float mine = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int base = halo_base(n, q, lz);
+        u16x8 B[2];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = 16 * ks + 4 * g + j;          // window offset of features 2j, 2j+1
+                uint32_t c0 = 0, c1 = 0;
+                if (o < kTaps) counts_of<L1>(img_s[base + halo_off_rt(o)], c0, c1);
+                else if (o == kTaps) c0 = 1;                 // feature 54: the constant 1
+                if (KM == kMfmaF16) {
+                    B[ks][2 * j] = __builtin_bit_cast(unsigned short, (_Float16)(float)c0);
+                    B[ks][2 * j + 1] = __builtin_bit_cast(unsigned short, (_Float16)(float)c1);
+                } else {   // small integers: the bf16 is the top half of the fp32 pattern, exactly
+                    B[ks][2 * j] = (unsigned short)(__float_as_uint((float)c0) >> 16);
+                    B[ks][2 * j + 1] = (unsigned short)(__float_as_uint((float)c1) >> 16);
+                }
+            }
+        }
+        f32x4 acc[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    if (KM == kMfmaF16)
+                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, A[p][mb][ks]),
+                                                                         __builtin_bit_cast(f16x8, B[ks]), acc[mb], 0, 0, 0);
+                    else
+                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[p][mb][ks]),
+                                                                          __builtin_bit_cast(bf16x8, B[ks]), acc[mb], 0, 0, 0);
+                }
+        }
+        float part = 0.0f;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = min(16 * mb + 4 * g + i, kTaps - 1);   // rows >= 27 hold zero kernels
+                part = fmaf(acc[mb][i], r_s[base + halo_off_rt(t)], part);
+            }
+        part += __shfl_xor(part, 16, 64);
+        part += __shfl_xor(part, 32, 64);
+        if (q == g) mine = part;
+    }
+    return mine;
+}
+
+// One CConv output of the thread's cell (lx, ly, lz) for a wave-uniform mode.
+template <class T, int KM, bool L1>
+__device__ inline T cconv_any(int mode, bool active, const uint32_t* img_s, const T* r_s, int base, int lz,
+                              const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
+                              const T* __restrict__ kst, size_t n, size_t idx) {
+    if (mode == -3) return T(0);
+    if (mode >= 0) return active ? cconv_pure<T>(r_s, base, w, mode) : T(0);
+    if constexpr (KM == kStored) {
+        return active ? cconv_stored<T>(r_s, base, kst, n, idx) : T(0);
+    } else if constexpr (KM == kVector) {
+        return active ? cconv_vector<T, L1>(img_s, r_s, base, w) : T(0);
+    } else {
+        static_assert(sizeof(T) == 4, "MFMA paths are float");
+        return cconv_mfma<KM, L1>(img_s, reinterpret_cast<const float*>(r_s), lz, wm);
+    }
+}
+
+// The mixed-BC 7-point matrix applied at `base` of a staged tile with row
+// stride (sx, sy): diagonal = fluid or air face neighbours (out of grid is
+// solid), -1 per fluid face neighbour, zero on non-fluid rows (Sec.
+// "Spatial Discretization").
+// sx: stride of y, sz: stride of z; Acc: accumulation type.
+template <class Acc, class V, class L>
+__device__ inline Acc apply_A(const L* lab_s, const V* v_s, int base, int sx, int sz) {
+    if (lab_s[base] != kFluid) return Acc(0);
+    const int nb[6] = {-sz, sz, -sx, sx, -1, 1};
+    int cnt = 0;
+    Acc s = Acc(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const uint32_t l = lab_s[base + nb[k]];
+        cnt += (l != (uint32_t)kSolid);
+        if (l == (uint32_t)kFluid) s += (Acc)v_s[base + nb[k]];
+    }
+    return (Acc)cnt * (Acc)v_s[base] - s;
+}
+
+// ---------------------------------------------------------------------------
+// setup kernels
+// ---------------------------------------------------------------------------
+__global__ void k_state_init(State* st, int max_iter, int fixed, int n_ortho) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        State s = {};
+        s.max_iter = max_iter;
+        s.fixed = fixed;
+        s.n_ortho = n_ortho;
+        s.scale = 1.0;
+        *st = s;
+    }
+}
+
+// Validate labels and b, count fluid cells, ||b||^2, x0 = 0.
+template <class X>
+__global__ __launch_bounds__(kBlock) void k_scan(const uint8_t* __restrict__ lab, const double* __restrict__ b,
+                                                 size_t n, X* x, double* partials) {
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};   // bb, n_fluid, bad labels, non-finite
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const uint8_t l = lab[i];
+        if (l > kSolid) v[2] += 1.0;
+        if (l == kFluid) {
+            const double bv = b[i];
+            v[1] += 1.0;
+            if (!isfinite(bv)) v[3] += 1.0;
+            else v[0] += bv * bv;
+        }
+        x[i] = X(0);
+    }
+    block_partials<kBlock>(v, partials);
+}
+
+// Counts of level l+1 from level l: sums of the 2x2x2 children.
+template <bool FROM_LABELS>
+__global__ __launch_bounds__(kBlock) void k_pool_counts(const void* __restrict__ in, Grid gin,
+                                                        uint32_t* __restrict__ out, Grid gout) {
+    const size_t n = ncells(gout);
+    for (size_t q = (size_t)blockIdx.x * kBlock + threadIdx.x; q < n; q += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(q % gout.nx), y = (int)((q / gout.nx) % gout.ny), z = (int)(q / ((size_t)gout.nx * gout.ny));
+        uint32_t n0 = 0, n1 = 0;
+        for (int k = 0; k < 8; ++k) {
+            const size_t c = cell_index(gin, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1));
+            if (FROM_LABELS) {
+                const uint8_t l = static_cast<const uint8_t*>(in)[c];
+                n0 += l == kFluid;
+                n1 += l == kAir;
+            } else {
+                const uint32_t v = static_cast<const uint32_t*>(in)[c];
+                n0 += v & 0xffffu;
+                n1 += v >> 16;
+            }
+        }
+        out[q] = n0 | (n1 << 16);
+    }
+}
+
+// The image-window sums of Aff_1^l and Aff_2^l (global means), in double.
+template <bool L1>
+__global__ __launch_bounds__(kBlock) void k_aff(const void* __restrict__ img, Grid g, double inv_full,
+                                                const AffW* __restrict__ a1, const AffW* __restrict__ a2,
+                                                double* partials) {
+    const size_t n = ncells(g);
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
+        for (int o = 0; o < kTaps; ++o) {
+            const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
+            double i0 = 0.0, i1 = 0.0, i2 = 1.0;   // solid padding
+            if (in_grid(g, qz, qy, qx)) {
+                const size_t q = cell_index(g, qz, qy, qx);
+                if (L1) {
+                    const uint8_t l = static_cast<const uint8_t*>(img)[q];
+                    i0 = l == kFluid;
+                    i1 = l == kAir;
+                } else {
+                    const uint32_t c = static_cast<const uint32_t*>(img)[q];
+                    i0 = (double)(c & 0xffffu) * inv_full;
+                    i1 = (double)(c >> 16) * inv_full;
+                }
+                i2 = 1.0 - i0 - i1;
+            }
+            v[0] += a1->w[0][o] * i0 + a1->w[1][o] * i1 + a1->w[2][o] * i2;
+            v[1] += a2->w[0][o] * i0 + a2->w[1][o] * i1 + a2->w[2][o] * i2;
+        }
+    }
+    block_partials<kBlock>(v, partials);
+}
+
+// K[t][cell] of one CConv block on one level, formed in double (setup).
+template <class T, bool L1>
+__global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ img, Grid g,
+                                                       const CConvW<double>* __restrict__ w, T* __restrict__ kst) {
+    const size_t n = ncells(g);
+    for (size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (size_t)gridDim.x * kBlock) {
+        const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
+        double K[kTaps];
+        for (int t = 0; t < kTaps; ++t) K[t] = w->C[t];
+        for (int o = 0; o < kTaps; ++o) {
+            const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
+            uint32_t c0 = 0, c1 = 0;   // solid padding: no fluid, no air
+            if (in_grid(g, qz, qy, qx)) {
+                const size_t q = cell_index(g, qz, qy, qx);
+                const uint32_t v = L1 ? (uint32_t)static_cast<const uint8_t*>(img)[q] : static_cast<const uint32_t*>(img)[q];
+                counts_of<L1>(v, c0, c1);
+            }
+            for (int t = 0; t < kTaps; ++t) K[t] += w->D[o][t][0] * (double)c0 + w->D[o][t][1] * (double)c1;
+        }
+        for (int t = 0; t < kTaps; ++t) kst[(size_t)t * n + p] = (T)K[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the one-block control kernel
+// ---------------------------------------------------------------------------
+// Sums nparts partials of kRedWidth doubles in block order and updates the
+// state for one stage of the iteration.
+template <int STAGE>
+__global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* __restrict__ partials, int nparts,
+                                                       int i0, int i1, int i2, int i3, double d0, double d1,
+                                                       double d2) {
+    if ((STAGE == kStageResidual || STAGE == kStageDots || STAGE == kStageStep) && st->done) return;
+    __shared__ double sh[kRedWidth][kCtlBlock / 64];
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += kCtlBlock) {
+#pragma unroll
+        for (int w = 0; w < kRedWidth; ++w) v[w] += partials[(size_t)b * kRedWidth + w];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int w = 0; w < kRedWidth; ++w) v[w] = wave_sum(v[w]);
+    if (lane == 0) {
+#pragma unroll
+        for (int w = 0; w < kRedWidth; ++w) sh[w][wid] = v[w];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int w = 0; w < kRedWidth; ++w) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < kCtlBlock / 64; ++i) s += sh[w][i];
+        v[w] = s;
+    }
+    if (STAGE == kStageScan) {            // d0 = tol
+        st->bb = v[0];
+        st->n_fluid = (int)v[1];
+        st->bad_label = (int)v[2];
+        st->nonfinite = (int)v[3];
+        st->tol2bb = d0 * d0 * v[0];
+    } else if (STAGE == kStageAff) {      // i0 = level index, d0/d1 = Aff biases, d2 = 27 n_l
+        st->c1[i0] = d0 + v[0] / d2;
+        st->c2[i0] = d1 + v[1] / d2;
+    } else if (STAGE == kStageResidual) { // ||b - A x_k||^2 of the iterate down_l1 just formed
+        const double rr = v[0];
+        const int iter = st->iter + (st->pending ? 1 : 0);
+        st->iter = iter;
+        st->xcur ^= 1;          // down_l1 wrote the other solution buffer
+        st->pending = 0;
+        st->rr = rr;
+        st->scale = rr > 0.0 ? 1.0 / sqrt(rr) : 0.0;
+        st->nprev = min(iter, st->n_ortho);
+        if (!isfinite(rr)) {
+            st->done = 1;
+            st->status = -6;   // NPS_EBREAKDOWN
+        } else if (!st->fixed && rr < st->tol2bb) {
+            st->done = 1;
+            st->status = 0;
+        } else if (iter >= st->max_iter) {
+            st->done = 1;
+            st->status = st->fixed ? 0 : 1;   // NPS_OK / NPS_NOT_CONVERGED
+        }
+    } else if (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
+        const int sl[kMaxOrtho] = {i0, i1, i2, i3};
+        for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
+    } else if (STAGE == kStageStep) {     // i0: ring slot of the new direction
+        const double dAd = v[0], rd = v[1];
+        st->dAd[i0] = dAd;
+        st->rd = rd;
+        if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) {
+            st->done = 1;
+            st->status = -6;   // NPS_EBREAKDOWN
+        } else {
+            st->alpha = rd / dAd;
+            st->pending = 1;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// network kernels (Alg. 2)
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ inline void pool_tile_to(const T* out_s, TileOrigin o, Grid g, T* rnext) {
+    if (threadIdx.x < kBlock / 8) {
+        const int cx = threadIdx.x % (TX / 2), cy = (threadIdx.x / (TX / 2)) % (TY / 2),
+                  cz = threadIdx.x / ((TX / 2) * (TY / 2));
+        const Grid gc = coarser(g);
+        const int gx = o.x0 / 2 + cx, gy = o.y0 / 2 + cy, gz = o.z0 / 2 + cz;
+        if (gx < gc.nx && gy < gc.ny && gz < gc.nz) {
+            T s = T(0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int fx = 2 * cx + (k & 1), fy = 2 * cy + ((k >> 1) & 1), fz = 2 * cz + (k >> 2);
+                s += out_s[(fz * TY + fy) * TX + fx];
+            }
+            rnext[cell_index(gc, gz, gy, gx)] = s * T(0.125);
+        }
+    }
+}
+
+// Level 1, first kernel of an iteration.  SOLVE: applies the pending update
+// x += alpha d, forms the literal residual r = b - A x over the tile and its
+// one-cell halo (x staged with a two-cell halo), writes x and r of the tile's
+// cells and their partial ||r||^2.  x is read from one of the two solution
+// buffers and written to the other (state.xcur selects), so no block reads a
+// value another block has already updated.  HOOK (nps_apply_precond): r is
+// the input, masked to fluid.  Then x1 = CConv_1^1(r) and r^2 = Pool(x1).
+template <class T, class X, int KM, bool HOOK>
+__global__ __launch_bounds__(kBlock) void k_down_l1(
+    const uint8_t* __restrict__ lab, Grid g, const double* __restrict__ b, X* xb0, X* xb1,
+    const T* __restrict__ dpend, T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
+    const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
+    const State* st, double* partials) {
+    if (!HOOK && st->done) return;
+    __shared__ uint32_t img_s[kHalo];
+    __shared__ T r_s[kHalo];
+    __shared__ T out_s[kBlock];
+    __shared__ uint8_t lab2_s[HOOK ? 1 : kHalo2];
+    __shared__ X x2_s[HOOK ? 1 : kHalo2];
+    const bool pend = !HOOK && st->pending;
+    const X alpha = HOOK ? X(0) : (X)st->alpha;
+    const int cur = HOOK ? 0 : st->xcur;
+    const X* __restrict__ x = cur ? xb1 : xb0;
+    X* __restrict__ xnew = cur ? xb0 : xb1;
+    const Tiles tl = tiles_of(g);
+    const size_t n = ncells(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<true>(img_s, lab, g, o);
+        if (HOOK) {
+            for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+                const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+                const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
+                T val = T(0);
+                if (in_grid(g, zz, yy, xx) && lab[cell_index(g, zz, yy, xx)] == kFluid) val = r[cell_index(g, zz, yy, xx)];
+                r_s[i] = val;
+            }
+        } else {
+            // x (+ alpha d) and labels over the two-cell halo
+            for (int i = threadIdx.x; i < kHalo2; i += kBlock) {
+                const int hx = i % H2X, hy = (i / H2X) % H2Y, hz = i / (H2X * H2Y);
+                const int xx = o.x0 + hx - 2, yy = o.y0 + hy - 2, zz = o.z0 + hz - 2;
+                X xv = X(0);
+                uint8_t l = kSolid;
+                if (in_grid(g, zz, yy, xx)) {
+                    const size_t q = cell_index(g, zz, yy, xx);
+                    l = lab[q];
+                    xv = x[q];
+                    if (pend) xv += alpha * (X)dpend[q];
+                }
+                lab2_s[i] = l;
+                x2_s[i] = xv;
+            }
+            __syncthreads();
+            // r = b - A x over the tile and its one-cell halo (zero off fluid / off grid)
+            for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+                const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+                const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
+                const int b2 = ((hz + 1) * H2Y + (hy + 1)) * H2X + (hx + 1);
+                double rv = 0.0;
+                if (in_grid(g, zz, yy, xx) && lab2_s[b2] == kFluid)
+                    rv = b[cell_index(g, zz, yy, xx)] - apply_A<double, X, uint8_t>(lab2_s, x2_s, b2, H2X, H2X * H2Y);
+                r_s[i] = (T)rv;
+            }
+        }
+        __syncthreads();
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        if (!HOOK && active) {
+            const int b2 = ((lz + 2) * H2Y + (ly + 2)) * H2X + (lx + 2);
+            xnew[idx] = x2_s[b2];
+            const T rv = r_s[base];
+            r[idx] = rv;
+            v[0] += (double)rv * (double)rv;
+        }
+        const int mode = choose_mode<true>(active, img_s, base, 1u, true, false);
+        const T out = cconv_any<T, KM, true>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        if (active) x1[idx] = out;
+        out_s[threadIdx.x] = active ? out : T(0);
+        __syncthreads();
+        pool_tile_to<T>(out_s, o, g, rnext);
+    }
+    if (!HOOK) block_partials<kBlock>(v, partials);
+}
+
+// x1 = CConv_1(r, I) on one level l >= 2, and (POOL) r_next = Pool(x1).
+template <class T, int KM, bool POOL>
+__global__ __launch_bounds__(kBlock) void k_down(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
+                                                 const T* __restrict__ rin, T* __restrict__ x1, T* __restrict__ rnext,
+                                                 const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
+                                                 const T* __restrict__ kst, const State* st) {
+    if (st->done) return;
+    __shared__ uint32_t img_s[kHalo];
+    __shared__ T r_s[kHalo];
+    __shared__ T out_s[kBlock];
+    const Tiles tl = tiles_of(g);
+    const size_t n = ncells(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<false>(img_s, cnt, g, o);
+        for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+            const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+            const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
+            r_s[i] = in_grid(g, zz, yy, xx) ? rin[cell_index(g, zz, yy, xx)] : T(0);
+        }
+        __syncthreads();
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const int mode = KM == kStored ? -1 : choose_mode<false>(active, img_s, base, full, false, false);
+        const T out = cconv_any<T, KM, false>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        if (active) x1[idx] = out;
+        if (POOL) {
+            out_s[threadIdx.x] = active ? out : T(0);
+            __syncthreads();
+            pool_tile_to<T>(out_s, o, g, rnext);
+        }
+    }
+}
+
+// Linear 2x upsampling weights along one axis (cell-centred, edges clamped):
+// fine f -> coarse j = f/2 (weight 3/4) and its neighbour on f's side (1/4).
+__device__ inline void up_axis(int f, int nc, int& j, int& jn) {
+    j = f >> 1;
+    jn = (f & 1) ? min(j + 1, nc - 1) : max(j - 1, 0);
+}
+
+template <class T>
+__device__ inline T interp_at(const T* __restrict__ xc, Grid gc, int z, int y, int x) {
+    int jx, jxn, jy, jyn, jz, jzn;
+    up_axis(x, gc.nx, jx, jxn);
+    up_axis(y, gc.ny, jy, jyn);
+    up_axis(z, gc.nz, jz, jzn);
+    const T a = T(0.75), b = T(0.25);
+    const T p00 = a * xc[cell_index(gc, jz, jy, jx)] + b * xc[cell_index(gc, jz, jy, jxn)];
+    const T p01 = a * xc[cell_index(gc, jz, jyn, jx)] + b * xc[cell_index(gc, jz, jyn, jxn)];
+    const T p10 = a * xc[cell_index(gc, jzn, jy, jx)] + b * xc[cell_index(gc, jzn, jy, jxn)];
+    const T p11 = a * xc[cell_index(gc, jzn, jyn, jx)] + b * xc[cell_index(gc, jzn, jyn, jxn)];
+    return a * (a * p00 + b * p01) + b * (a * p10 + b * p11);
+}
+
+// Stage Interp(xc) over the haloed tile (zero outside the level's grid: the
+// zero padding of the CConv input).
+template <class T>
+__device__ inline void stage_interp(T* r_s, const T* __restrict__ xc, Grid g, TileOrigin o) {
+    const Grid gc = coarser(g);
+    for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+        const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
+        r_s[i] = in_grid(g, zz, yy, xx) ? interp_at<T>(xc, gc, zz, yy, xx) : T(0);
+    }
+}
+
+// x = c1 x1 + c2 CConv_2(Interp(xc), I) on one level l >= 2.
+template <class T, int KM>
+__global__ __launch_bounds__(kBlock) void k_up(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
+                                               const T* __restrict__ xc, const T* __restrict__ x1,
+                                               T* __restrict__ xout, const CConvW<T>* __restrict__ w,
+                                               const MfmaW* __restrict__ wm, const T* __restrict__ kst, int lvl,
+                                               const State* st) {
+    if (st->done) return;
+    __shared__ uint32_t img_s[kHalo];
+    __shared__ T r_s[kHalo];
+    const T c1 = (T)st->c1[lvl], c2 = (T)st->c2[lvl];
+    const Tiles tl = tiles_of(g);
+    const size_t n = ncells(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<false>(img_s, cnt, g, o);
+        stage_interp<T>(r_s, xc, g, o);
+        __syncthreads();
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const int mode = KM == kStored ? -1 : choose_mode<false>(active, img_s, base, full, false, false);
+        const T x2 = cconv_any<T, KM, false>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        if (active) xout[idx] = c1 * x1[idx] + c2 * x2;
+    }
+}
+
+// Level 1 of the up sweep: dhat = (c1 x1 + c2 CConv_2(Interp(x^2))) / ||r|| on
+// fluid cells (0 elsewhere), and the partial dots dhat . A d_i with the
+// stored A d_i of the previous directions.
+template <class T, int KM, bool HOOK>
+__global__ __launch_bounds__(kBlock) void k_up_l1(
+    const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ xc, const T* __restrict__ x1,
+    T* __restrict__ dhat, const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
+    const T* __restrict__ kst, const State* st, double* partials, const T* __restrict__ ad0,
+    const T* __restrict__ ad1, const T* __restrict__ ad2, const T* __restrict__ ad3) {
+    if (!HOOK && st->done) return;
+    __shared__ uint32_t img_s[kHalo];
+    __shared__ T r_s[kHalo];
+    const T c1 = (T)st->c1[0], c2 = (T)st->c2[0];
+    const T scale = HOOK ? T(1) : (T)st->scale;
+    const int nprev = HOOK ? 0 : st->nprev;
+    const Tiles tl = tiles_of(g);
+    const size_t n = ncells(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<true>(img_s, lab, g, o);
+        stage_interp<T>(r_s, xc, g, o);
+        __syncthreads();
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const int mode = choose_mode<true>(active, img_s, base, 1u, false, true);
+        const T x2 = cconv_any<T, KM, true>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        if (active) {
+            T out = T(0);
+            if (img_s[base] == (uint32_t)kFluid) out = (c1 * x1[idx] + c2 * x2) * scale;
+            dhat[idx] = out;
+            if (!HOOK) {
+                if (nprev > 0) v[0] += (double)out * (double)ad0[idx];
+                if (nprev > 1) v[1] += (double)out * (double)ad1[idx];
+                if (nprev > 2) v[2] += (double)out * (double)ad2[idx];
+                if (nprev > 3) v[3] += (double)out * (double)ad3[idx];
+            }
+        }
+    }
+    if (!HOOK) block_partials<kBlock>(v, partials);
+}
+
+// The smallest levels lb..L in one workgroup, in LDS, with stored kernels:
+// down sweep (CConv_1 + pool), coarsest CConv_1, up sweep (Interp + CConv_2 +
+// combine).  Reads r^lb, writes x^lb.
+template <class T>
+struct BottomArgs {
+    int lb, L;
+    Grid g[kMaxLevels + 1];
+    const T* k1[kMaxLevels + 1];
+    const T* k2[kMaxLevels + 1];
+    const T* rin;
+    T* xout;
+};
+
+constexpr int kBottomThreads = 256;
+constexpr int kBottomLds = 2 * 640;   // >= 2 * sum of the bottom levels' cells
+
+template <class T>
+__device__ inline T bottom_get(const T* v, Grid g, int z, int y, int x) {
+    return in_grid(g, z, y, x) ? v[cell_index(g, z, y, x)] : T(0);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, const State* st) {
+    if (st->done) return;
+    __shared__ T buf[kBottomLds];
+    T* rb[kMaxLevels + 2];    // r^l, then x^l (up sweep output)
+    T* x1[kMaxLevels + 2];
+    int off = 0;
+    for (int l = a.lb; l <= a.L; ++l) {
+        const int nl = (int)ncells(a.g[l]);
+        rb[l] = buf + off;
+        off += nl;
+        x1[l] = buf + off;
+        off += nl;
+    }
+    {
+        const int nl = (int)ncells(a.g[a.lb]);
+        for (int i = threadIdx.x; i < nl; i += kBottomThreads) rb[a.lb][i] = a.rin[i];
+    }
+    __syncthreads();
+    for (int l = a.lb; l <= a.L; ++l) {       // down sweep and coarsest level
+        const Grid g = a.g[l];
+        const int nl = (int)ncells(g);
+        for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
+            const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+            T acc = T(0);
+            for (int t = 0; t < kTaps; ++t)
+                acc = fma(a.k1[l][(size_t)t * nl + p], bottom_get(rb[l], g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+            x1[l][p] = acc;
+        }
+        __syncthreads();
+        if (l < a.L) {
+            const Grid gc = coarser(g);
+            const int nc = (int)ncells(gc);
+            for (int q = threadIdx.x; q < nc; q += kBottomThreads) {
+                const int x = q % gc.nx, y = (q / gc.nx) % gc.ny, z = q / (gc.nx * gc.ny);
+                T s = T(0);
+                for (int k = 0; k < 8; ++k) s += x1[l][cell_index(g, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1))];
+                rb[l + 1][q] = s * T(0.125);
+            }
+            __syncthreads();
+        }
+    }
+    // up sweep: x^L = x1^L
+    const T* xc = x1[a.L];
+    for (int l = a.L - 1; l >= a.lb; --l) {
+        const Grid g = a.g[l], gc = a.g[l + 1];
+        const int nl = (int)ncells(g);
+        const T c1 = (T)st->c1[l - 1], c2 = (T)st->c2[l - 1];
+        for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
+            const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+            T acc = T(0);
+            for (int t = 0; t < kTaps; ++t) {
+                const int qz = z + t / 9 - 1, qy = y + (t / 3) % 3 - 1, qx = x + t % 3 - 1;
+                const T rv = in_grid(g, qz, qy, qx) ? interp_at<T>(xc, gc, qz, qy, qx) : T(0);
+                acc = fma(a.k2[l][(size_t)t * nl + p], rv, acc);
+            }
+            rb[l][p] = c1 * x1[l][p] + c2 * acc;
+        }
+        __syncthreads();
+        xc = rb[l];
+    }
+    {   // x^lb (x1^L itself when the bottom holds only the coarsest level)
+        const int nl = (int)ncells(a.g[a.lb]);
+        for (int i = threadIdx.x; i < nl; i += kBottomThreads) a.xout[i] = xc[i];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Krylov kernels (Alg. 1)
+// ---------------------------------------------------------------------------
+// d = dhat - sum_j beta_j d_(k-1-j) (classical Gram-Schmidt in the A inner
+// product; equal to the paper's sequential update because the directions in
+// the window are already mutually A-orthogonal), A d, and the partial dots
+// d . A d and r . d.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ dhat,
+                                                  const T* __restrict__ p0, const T* __restrict__ p1,
+                                                  const T* __restrict__ p2, const T* __restrict__ p3,
+                                                  const T* __restrict__ r, T* __restrict__ dout, T* __restrict__ adout,
+                                                  const State* st, double* partials) {
+    if (st->done) return;
+    __shared__ uint32_t lab_s[kHalo];
+    __shared__ T d_s[kHalo];
+    const int nprev = st->nprev;
+    const T b0 = (T)st->beta[0], b1 = (T)st->beta[1], b2 = (T)st->beta[2], b3 = (T)st->beta[3];
+    const Tiles tl = tiles_of(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<true>(lab_s, lab, g, o);
+        for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+            const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+            const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
+            T dv = T(0);
+            if (in_grid(g, zz, yy, xx)) {
+                const size_t q = cell_index(g, zz, yy, xx);
+                dv = dhat[q];
+                if (nprev > 0) dv -= b0 * p0[q];
+                if (nprev > 1) dv -= b1 * p1[q];
+                if (nprev > 2) dv -= b2 * p2[q];
+                if (nprev > 3) dv -= b3 * p3[q];
+            }
+            d_s[i] = dv;
+        }
+        __syncthreads();
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        if (in_grid(g, zz, yy, xx)) {
+            const size_t idx = cell_index(g, zz, yy, xx);
+            const T dv = d_s[base];
+            const T ad = apply_A<T, T, uint32_t>(lab_s, d_s, base, HX, HX * HY);
+            dout[idx] = dv;
+            adout[idx] = ad;
+            v[0] += (double)dv * (double)ad;
+            v[1] += (double)r[idx] * (double)dv;
+        }
+    }
+    block_partials<kBlock>(v, partials);
+}
+
+// x_out = x (the current solution buffer) on fluid cells, 0 elsewhere, in double.
+template <class X>
+__global__ __launch_bounds__(kBlock) void k_finalize(size_t n, const uint8_t* __restrict__ lab, const X* xb0,
+                                                     const X* xb1, const State* st, double* __restrict__ xout) {
+    const X* __restrict__ x = st->xcur ? xb1 : xb0;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+        xout[i] = lab[i] == kFluid ? (double)x[i] : 0.0;
+}
+
+// y = A x (parity hook; same stencil code as the solve).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_laplacian(const uint8_t* __restrict__ lab, Grid g,
+                                                      const T* __restrict__ x, T* __restrict__ y) {
+    __shared__ uint32_t lab_s[kHalo];
+    __shared__ T x_s[kHalo];
+    const Tiles tl = tiles_of(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<true>(lab_s, lab, g, o);
+        for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+            const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
+            const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, z = o.z0 + hz - 1;
+            x_s[i] = in_grid(g, z, yy, xx) ? x[cell_index(g, z, yy, xx)] : T(0);
+        }
+        __syncthreads();
+        const int xx = o.x0 + lx, yy = o.y0 + ly, z = o.z0 + lz;
+        if (in_grid(g, z, yy, xx)) y[cell_index(g, z, yy, xx)] = apply_A<T, T, uint32_t>(lab_s, x_s, base, HX, HX * HY);
+    }
+}
+
+}  // namespace nps
