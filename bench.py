@@ -40,9 +40,16 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--headline", default="mixed_bf16", choices=["mixed_bf16", "mixed_fp16", "fp32", "fp64"])
-    ap.add_argument("--compare", default="fp32")
+    ap.add_argument("--compare", default="fp32", help="second precision to time, or 'none'")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="end with one 256 MiB device-to-device copy (a known-size kernel for HBM counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations in the CPU sample")
+    ap.add_argument("--serving", action="store_true",
+                    help="run the request-server sweep instead (Poisson arrivals, mixed grid sizes)")
+    ap.add_argument("--requests", type=int, default=512)
+    ap.add_argument("--qps", type=float, nargs="+", default=[20.0, 50.0, 100.0])
+    ap.add_argument("--slots", type=int, default=16)
     return ap.parse_args()
 
 
@@ -100,8 +107,82 @@ def cpu_baseline(labels, b, params, iters_sample):
                       f"{ref['iterations']}-iteration solve of this workload"}
 
 
+def serving_sweep(args):
+    """Continuous-batching server: `requests` solves with Poisson arrivals at each
+    QPS, grids drawn uniformly from {64,96,128,160}^3, tol 1e-6, mixed bf16."""
+    import torch
+
+    import nps_inputs as gi
+    import paper_2310_00177_amd as nps
+
+    torch.cuda.set_device(0)
+    sizes = [64, 96, 128, 160]
+    net = nps.Net(gi.multilevel_params(6), 6)
+    # a pool of distinct scenes (4 per size) and right-hand sides (2 per scene), reused cyclically
+    pool = []
+    for n in sizes:
+        for j in range(4):
+            lab = gi.gen_labels(gi.scene_serving(n), seed=10000 + 10 * n + j)
+            for k in range(2):
+                pool.append((n, lab, gi.gen_rhs(lab, seed=20000 + 10 * n + 2 * j + k)))
+    print(f"# serving: pool of {len(pool)} requests ready", file=sys.stderr, flush=True)
+    rng = np.random.default_rng(77)
+    results = []
+    for qps in args.qps:
+        srv = nps.Server(net, hbm_budget=64 << 30, max_slots=args.slots)
+        picks = [pool[i] for i in rng.integers(0, len(pool), size=args.requests)]
+        gaps = rng.exponential(1.0 / qps, size=args.requests)
+        arrivals = np.cumsum(gaps) - gaps[0]
+        # warm-up: one request of each size
+        for n in sizes:
+            lab, b = next((p[1], p[2]) for p in pool if p[0] == n)
+            rid = srv.submit(lab, b)
+            while srv.poll(rid) is None:
+                srv.step()
+        lat, its, ok, inflight, peak = [], [], 0, {}, 0
+        t0 = time.perf_counter()
+        i = 0
+        t_end = t0
+        while len(lat) < args.requests:
+            now = time.perf_counter() - t0
+            while i < args.requests and arrivals[i] <= now:
+                n, lab, b = picks[i]
+                inflight[srv.submit(lab, b)] = n
+                i += 1
+            active, queued = srv.step()
+            peak = max(peak, active)
+            for rid in list(inflight):
+                r = srv.poll(rid)
+                if r is not None:
+                    x, info, ms = r
+                    lat.append(ms)
+                    its.append(info.iterations)
+                    ok += info.status == 0 and info.rel_residual < 1e-6
+                    del inflight[rid]
+                    t_end = time.perf_counter()
+        wall = t_end - t0
+        srv.close()
+        lat = np.array(lat)
+        row = {"qps": qps, "throughput": args.requests / wall, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "mean_iterations": float(np.mean(its)),
+               "converged": int(ok), "peak_active": int(peak)}
+        print(f"# serving qps {qps}: {row}", file=sys.stderr, flush=True)
+        results.append(row)
+    out = {"metric": "served solves/sec to 1e-6 rel. residual, grids {64,96,128,160}^3; p50/p99 latency",
+           "value": max(r["throughput"] for r in results), "unit": "solves/s", "n_gpus": 1,
+           "higher_is_better": True, "dtype": "bf16+f32+f64", "data": "synthetic",
+           "config": {"workload": f"{args.requests} requests per QPS, Poisson arrivals, grids uniform in "
+                                  f"{{64,96,128,160}}^3 from a pool of 16 scenes x 2 RHS, tol 1e-6, L=6, "
+                                  f"n_ortho=2, mixed bf16, {args.slots} slots", "weights": "multilevel"},
+           "sweep": results}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.serving and args.gpus == 1:
+        serving_sweep(args)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this solver runs a single solve per GPU and the build has "
               f"no multi-GPU path (asked for --gpus {args.gpus})", file=sys.stderr)
@@ -154,7 +235,7 @@ def main():
 
     head, ws_h, x_h = run(args.headline, args.steps, args.warmup)
     comp = None
-    if args.compare and args.compare != args.headline:
+    if args.compare and args.compare not in ("none", args.headline):
         comp, _, _ = run(args.compare, args.steps, args.warmup)
 
     # profiled pass: per-kernel durations from HIP events on the launch stream
@@ -230,6 +311,13 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("# calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr)
 
 
 if __name__ == "__main__":

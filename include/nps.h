@@ -142,6 +142,58 @@ int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims
                       const void* r_d, void* d_d, int precision,
                       void* ws_d, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Request server: continuous batching of solves of different grids.
+ *
+ * The server owns one device arena (hbm_budget bytes, allocated once by
+ * nps_server_create) and up to max_slots streams.  nps_server_submit copies
+ * a request's labels and b into server-owned pinned host memory and queues
+ * it (first in, first out).  nps_server_step never blocks: it admits queued
+ * requests while the arena has room for their footprint
+ * (nps_server_request_bytes) and a slot is free, and advances every admitted
+ * request by at most one NPSDO iteration on its own stream, so iterations of
+ * different requests overlap on the device.  A finished request leaves its
+ * slot and its arena space at once; nps_server_poll returns NPS_PENDING (2)
+ * until its result is ready, then copies x (double, full grid) to x_h,
+ * fills *info, *latency_ms (submission to completion) and releases the
+ * request.  Every request is solved exactly as nps_solve would solve it
+ * alone (same kernels, same per-request reductions): results do not depend
+ * on what else is in flight.  Not thread-safe: one host thread per server.
+ * ------------------------------------------------------------------------ */
+enum { NPS_PENDING = 2 };
+typedef struct nps_server nps_server;
+
+int nps_server_create(const nps_net* net, size_t hbm_budget, int max_slots, nps_server** out);
+void nps_server_destroy(nps_server* srv);
+size_t nps_server_request_bytes(const nps_server* srv, nps_dims dims, const nps_opts* opts);
+int nps_server_submit(nps_server* srv, const uint8_t* labels_h, nps_dims dims, const double* b_h,
+                      const nps_opts* opts, uint64_t* req_id);
+/* *n_active: requests on the device after the step; *n_queued: waiting. */
+int nps_server_step(nps_server* srv, int* n_active, int* n_queued);
+int nps_server_poll(nps_server* srv, uint64_t req_id, double* x_h, nps_info* info, double* latency_ms);
+
+/* ------------------------------------------------------------------------
+ * Training (loss of Sec. "Training": || b - A P(I, b) ||_2 per system).
+ * precision NPS_FP64 (double vectors) or NPS_FP32 (float vectors); every
+ * level keeps its per-cell kernels in the workspace.
+ *   nps_net_forward   y = P(I, r); keeps the per-level activations (the
+ *                     down inputs, x1, the up outputs, the CConv_2 outputs)
+ *                     in ws for the backward pass of the same system.
+ *   nps_train_loss    res = b - A y on fluid, *loss_h = ||res||_2 (host),
+ *                     gy = dL/dy = -A res / ||res|| (A is symmetric).
+ *   nps_net_backward  adds dL/dparams (double, nps_param_count(levels),
+ *                     blob layout of nps_net_create) into grad_d, given r
+ *                     (the forward input) and gy; uses the activations the
+ *                     last nps_net_forward left in ws.  Not synchronised.
+ * ------------------------------------------------------------------------ */
+size_t nps_train_workspace_bytes(nps_dims dims, int levels, int precision);
+int nps_net_forward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, void* y_d,
+                    int precision, void* ws_d, size_t ws_bytes, void* stream);
+int nps_train_loss(const uint8_t* labels_d, nps_dims dims, int levels, const void* b_d, const void* y_d,
+                   void* gy_d, double* loss_h, int precision, void* ws_d, size_t ws_bytes, void* stream);
+int nps_net_backward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d,
+                     const void* gy_d, double* grad_d, int precision, void* ws_d, size_t ws_bytes, void* stream);
+
 /* Per-kernel timing.  While enabled (on != 0, per calling thread), every
  * kernel the library launches is bracketed by a pair of HIP events recorded
  * on the launch stream.  nps_profile_read synchronises those events, writes

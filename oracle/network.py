@@ -205,13 +205,14 @@ class Network:
         xs = [None] * L
         xs[L - 1] = x
         r2 = [None] * (L - 1)
+        x2s = [None] * (L - 1)
         for l in range(L - 2, -1, -1):               # up sweep
             r2[l] = interpolate(x)
-            x2 = cconv_apply(self.K2[l], r2[l])
-            x = self.c1[l] * x1[l] + self.c2[l] * x2
+            x2s[l] = cconv_apply(self.K2[l], r2[l])
+            x = self.c1[l] * x1[l] + self.c2[l] * x2s[l]
             xs[l] = x
         if acts is not None:
-            acts.update(r1=r1, x1=x1, r2=r2, x=xs)
+            acts.update(r1=r1, x1=x1, r2=r2, x2=x2s, x=xs)
         return np.where(self.fluid, x, 0.0)
 
 

@@ -19,7 +19,8 @@ from . import _lib
 from ._lib import (NPS_FP64 as FP64, NPS_FP32 as FP32, NPS_MIXED_BF16 as MIXED_BF16,  # noqa: F401
                    NPS_MIXED_FP16 as MIXED_FP16, STATUS_NAMES)
 
-__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "NpsError", "SolveInfo",
+__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "NpsError", "SolveInfo", "Server",
+           "train_workspace", "net_forward", "net_backward", "train_loss", "Precond", "TrainLoss",
            "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "workspace", "vector_dtype"]
 
 
@@ -156,3 +157,155 @@ def apply_precond(net: Net, labels: torch.Tensor, r: torch.Tensor, precision: in
     if rc != _lib.NPS_OK:
         raise NpsError(rc, "nps_apply_precond")
     return d
+
+
+class Server:
+    """Continuous-batching request server (nps_server_* in the C ABI).
+
+    submit() copies a request's host arrays and queues it; step() admits
+    requests by HBM footprint and advances every admitted one by at most one
+    iteration on its own stream; poll() returns (x, info, latency_ms) once a
+    request has finished, else None.
+    """
+
+    def __init__(self, net: Net, hbm_budget: int, max_slots: int = 8):
+        self.net = net   # keeps the network alive
+        rc, h = _lib.nps_server_create(net.handle, int(hbm_budget), int(max_slots))
+        if rc != _lib.NPS_OK:
+            raise NpsError(rc, "nps_server_create")
+        self.handle = h
+        self._shapes = {}
+
+    def request_bytes(self, shape, tol=1e-6, max_iter=1000, n_ortho=2, precision=MIXED_BF16) -> int:
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 0)
+        return _lib.nps_server_request_bytes(self.handle, _dims(shape), opts)
+
+    def submit(self, labels: np.ndarray, b: np.ndarray, tol: float = 1e-6, max_iter: int = 1000,
+               n_ortho: int = 2, precision: int = MIXED_BF16, fixed_iters: bool = False) -> int:
+        lab = np.ascontiguousarray(labels, dtype=np.uint8)
+        bb = np.ascontiguousarray(b, dtype=np.float64)
+        if lab.shape != bb.shape or lab.ndim != 3:
+            raise ValueError("labels and b must be (nz, ny, nx) arrays of one shape")
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 1 if fixed_iters else 0)
+        rc, rid = _lib.nps_server_submit(self.handle, lab.ctypes.data, _dims(lab.shape), bb.ctypes.data, opts)
+        if rc != _lib.NPS_OK:
+            raise NpsError(rc, "nps_server_submit")
+        self._shapes[rid] = lab.shape
+        return rid
+
+    def step(self) -> tuple:
+        rc, active, queued = _lib.nps_server_step(self.handle)
+        if rc != _lib.NPS_OK:
+            raise NpsError(rc, "nps_server_step")
+        return active, queued
+
+    def poll(self, rid: int):
+        shape = self._shapes[rid]
+        x = np.empty(shape, dtype=np.float64)
+        info = _lib.nps_info()
+        rc, lat = _lib.nps_server_poll(self.handle, rid, x.ctypes.data, info)
+        if rc == _lib.NPS_PENDING:
+            return None
+        del self._shapes[rid]
+        return x, SolveInfo(info.iterations, rc, info.rel_residual, info.rel_residual_rec, info.refinements,
+                            info.n_fluid), lat
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.nps_server_destroy(h)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+# ---------------------------------------------------------------------------
+# training (loss of Sec. "Training")
+# ---------------------------------------------------------------------------
+def train_workspace(shape, levels: int, precision: int, device="cuda") -> torch.Tensor:
+    nbytes = _lib.nps_train_workspace_bytes(_dims(shape), levels, precision)
+    return torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+
+
+def _ws_args(ws: torch.Tensor):
+    return _aligned(ws), ws.numel() - (_aligned(ws) - ws.data_ptr())
+
+
+def net_forward(net: Net, labels: torch.Tensor, r: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
+    """y = P(I, r); the activations stay in ws for net_backward."""
+    _check_device(labels, r)
+    prec = FP64 if r.dtype == torch.float64 else FP32
+    y = torch.empty_like(r)
+    wp, wb = _ws_args(ws)
+    rc = _lib.nps_net_forward(net.handle, labels.data_ptr(), _dims(labels.shape), r.data_ptr(), y.data_ptr(), prec,
+                              wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_net_forward")
+    return y
+
+
+def train_loss(labels: torch.Tensor, b: torch.Tensor, y: torch.Tensor, levels: int, ws: torch.Tensor):
+    """(loss, dL/dy) of || b - A y ||_2."""
+    _check_device(labels, b, y)
+    prec = FP64 if y.dtype == torch.float64 else FP32
+    gy = torch.empty_like(y)
+    wp, wb = _ws_args(ws)
+    rc, loss = _lib.nps_train_loss(labels.data_ptr(), _dims(labels.shape), levels, b.data_ptr(), y.data_ptr(),
+                                   gy.data_ptr(), prec, wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_train_loss")
+    return loss, gy
+
+
+def net_backward(net: Net, labels: torch.Tensor, r: torch.Tensor, gy: torch.Tensor, grad: torch.Tensor,
+                 ws: torch.Tensor) -> torch.Tensor:
+    """grad += dL/dparams (float64 device tensor of nps_param_count entries)."""
+    _check_device(labels, r, gy, grad)
+    prec = FP64 if r.dtype == torch.float64 else FP32
+    wp, wb = _ws_args(ws)
+    rc = _lib.nps_net_backward(net.handle, labels.data_ptr(), _dims(labels.shape), r.data_ptr(), gy.data_ptr(),
+                               grad.data_ptr(), prec, wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_net_backward")
+    return grad
+
+
+class Precond(torch.autograd.Function):
+    """y = P(I, r) with the library's forward and hand-written backward.
+
+    params: float64 tensor (nps_param_count(levels)); the gradient flows to it.
+    Each call keeps its own activation workspace until backward."""
+
+    @staticmethod
+    def forward(ctx, params, labels, r, levels):
+        net = Net(params.detach().cpu().numpy(), levels, device=r.device)
+        ws = train_workspace(labels.shape, levels, FP64 if r.dtype == torch.float64 else FP32, device=r.device)
+        y = net_forward(net, labels, r.contiguous(), ws)
+        ctx.net, ctx.ws, ctx.labels, ctx.levels = net, ws, labels, levels
+        ctx.save_for_backward(r)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        (r,) = ctx.saved_tensors
+        grad = torch.zeros(_lib.nps_param_count(ctx.levels), dtype=torch.float64, device=r.device)
+        net_backward(ctx.net, ctx.labels, r.contiguous(), gy.contiguous().to(r.dtype), grad, ctx.ws)
+        ctx.ws = None
+        return grad, None, None, None
+
+
+class TrainLoss(torch.autograd.Function):
+    """loss = || b - A y ||_2 (A the mixed-BC matrix of the labels)."""
+
+    @staticmethod
+    def forward(ctx, y, labels, b, levels):
+        ws = train_workspace(labels.shape, levels, FP64 if y.dtype == torch.float64 else FP32, device=y.device)
+        loss, gy = train_loss(labels, b.contiguous(), y.contiguous(), levels, ws)
+        ctx.save_for_backward(gy)
+        return torch.tensor(loss, dtype=torch.float64, device=y.device)
+
+    @staticmethod
+    def backward(ctx, gl):
+        (gy,) = ctx.saved_tensors
+        return gy * gl.to(gy.dtype), None, None, None

@@ -66,14 +66,37 @@ _lib.nps_apply_laplacian.argtypes = [_vp, nps_dims, _vp, _vp, _int, _vp]
 _lib.nps_apply_laplacian.restype = _int
 _lib.nps_apply_precond.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _int, _vp, _sz, _vp]
 _lib.nps_apply_precond.restype = _int
+_u64 = ctypes.c_uint64
+_lib.nps_server_create.argtypes = [_vp, _sz, _int, ctypes.POINTER(_vp)]
+_lib.nps_server_create.restype = _int
+_lib.nps_server_destroy.argtypes, _lib.nps_server_destroy.restype = [_vp], None
+_lib.nps_server_request_bytes.argtypes = [_vp, nps_dims, ctypes.POINTER(nps_opts)]
+_lib.nps_server_request_bytes.restype = _sz
+_lib.nps_server_submit.argtypes = [_vp, _vp, nps_dims, _vp, ctypes.POINTER(nps_opts), ctypes.POINTER(_u64)]
+_lib.nps_server_submit.restype = _int
+_lib.nps_server_step.argtypes = [_vp, ctypes.POINTER(_int), ctypes.POINTER(_int)]
+_lib.nps_server_step.restype = _int
+_lib.nps_server_poll.argtypes = [_vp, _u64, _vp, ctypes.POINTER(nps_info), ctypes.POINTER(ctypes.c_double)]
+_lib.nps_server_poll.restype = _int
+_lib.nps_train_workspace_bytes.argtypes = [nps_dims, _int, _int]
+_lib.nps_train_workspace_bytes.restype = _sz
+_lib.nps_net_forward.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _int, _vp, _sz, _vp]
+_lib.nps_net_forward.restype = _int
+_lib.nps_train_loss.argtypes = [_vp, nps_dims, _int, _vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _int, _vp, _sz, _vp]
+_lib.nps_train_loss.restype = _int
+_lib.nps_net_backward.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _vp, _int, _vp, _sz, _vp]
+_lib.nps_net_backward.restype = _int
 _lib.nps_profile_enable.argtypes, _lib.nps_profile_enable.restype = [_int], _int
 _lib.nps_profile_read.argtypes = [ctypes.POINTER(nps_kernel_stat), _int, ctypes.POINTER(_int)]
 _lib.nps_profile_read.restype = _int
 _lib.nps_last_error.argtypes, _lib.nps_last_error.restype = [], ctypes.c_char_p
 
 EXPORTED = ["nps_param_count", "nps_net_bytes", "nps_net_create", "nps_net_destroy", "nps_net_levels",
-            "nps_workspace_bytes", "nps_solve", "nps_apply_laplacian", "nps_apply_precond", "nps_profile_enable",
-            "nps_profile_read", "nps_last_error"]
+            "nps_workspace_bytes", "nps_solve", "nps_apply_laplacian", "nps_apply_precond", "nps_server_create",
+            "nps_server_destroy", "nps_server_request_bytes", "nps_server_submit", "nps_server_step",
+            "nps_server_poll", "nps_train_workspace_bytes", "nps_net_forward", "nps_train_loss", "nps_net_backward",
+            "nps_profile_enable", "nps_profile_read", "nps_last_error"]
+NPS_PENDING = 2
 
 
 def nps_param_count(levels: int) -> int:
@@ -117,6 +140,65 @@ def nps_apply_laplacian(labels_d: int, dims: nps_dims, x_d: int, y_d: int, preci
 def nps_apply_precond(net: int, labels_d: int, dims: nps_dims, r_d: int, d_d: int, precision: int,
                       ws_d: int, ws_bytes: int, stream: int) -> int:
     return _lib.nps_apply_precond(net, labels_d, dims, r_d, d_d, precision, ws_d, ws_bytes, stream)
+
+
+def nps_server_create(net: int, hbm_budget: int, max_slots: int) -> tuple:
+    """Returns (status, server handle)."""
+    out = _vp()
+    rc = _lib.nps_server_create(net, hbm_budget, max_slots, ctypes.byref(out))
+    return rc, out.value
+
+
+def nps_server_destroy(srv: int) -> None:
+    _lib.nps_server_destroy(srv)
+
+
+def nps_server_request_bytes(srv: int, dims: nps_dims, opts: nps_opts) -> int:
+    return _lib.nps_server_request_bytes(srv, dims, ctypes.byref(opts))
+
+
+def nps_server_submit(srv: int, labels_h: int, dims: nps_dims, b_h: int, opts: nps_opts) -> tuple:
+    """Returns (status, request id)."""
+    rid = _u64(0)
+    rc = _lib.nps_server_submit(srv, labels_h, dims, b_h, ctypes.byref(opts), ctypes.byref(rid))
+    return rc, rid.value
+
+
+def nps_server_step(srv: int) -> tuple:
+    """Returns (status, n_active, n_queued)."""
+    a, q = _int(0), _int(0)
+    rc = _lib.nps_server_step(srv, ctypes.byref(a), ctypes.byref(q))
+    return rc, a.value, q.value
+
+
+def nps_server_poll(srv: int, req_id: int, x_h: int, info: nps_info) -> tuple:
+    """Returns (status, latency_ms); status NPS_PENDING while the request runs."""
+    lat = ctypes.c_double(0.0)
+    rc = _lib.nps_server_poll(srv, req_id, x_h, ctypes.byref(info), ctypes.byref(lat))
+    return rc, lat.value
+
+
+def nps_train_workspace_bytes(dims: nps_dims, levels: int, precision: int) -> int:
+    return _lib.nps_train_workspace_bytes(dims, levels, precision)
+
+
+def nps_net_forward(net: int, labels_d: int, dims: nps_dims, r_d: int, y_d: int, precision: int, ws_d: int,
+                    ws_bytes: int, stream: int) -> int:
+    return _lib.nps_net_forward(net, labels_d, dims, r_d, y_d, precision, ws_d, ws_bytes, stream)
+
+
+def nps_train_loss(labels_d: int, dims: nps_dims, levels: int, b_d: int, y_d: int, gy_d: int, precision: int,
+                   ws_d: int, ws_bytes: int, stream: int) -> tuple:
+    """Returns (status, loss)."""
+    loss = ctypes.c_double(0.0)
+    rc = _lib.nps_train_loss(labels_d, dims, levels, b_d, y_d, gy_d, ctypes.byref(loss), precision, ws_d, ws_bytes,
+                             stream)
+    return rc, loss.value
+
+
+def nps_net_backward(net: int, labels_d: int, dims: nps_dims, r_d: int, gy_d: int, grad_d: int, precision: int,
+                     ws_d: int, ws_bytes: int, stream: int) -> int:
+    return _lib.nps_net_backward(net, labels_d, dims, r_d, gy_d, grad_d, precision, ws_d, ws_bytes, stream)
 
 
 def nps_profile_enable(on: int) -> int:

@@ -10,9 +10,14 @@
 #include "nps.h"
 #include "nps_internal.hpp"
 #include "nps_kernels.hpp"
+#include "nps_train_kernels.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <deque>
+#include <map>
+#include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -84,12 +89,16 @@ struct Plan {
     int km[kMaxLevels + 2];      // KMode per level
 };
 
-Plan make_plan(nps_dims d, int levels, int precision) {
+Plan make_plan(nps_dims d, int levels, int precision, bool all_stored = false) {
     Plan p = {};
     p.L = levels;
     p.lb = levels + 1;
     for (int l = 1; l <= levels; ++l) {
         const size_t n = ncells(level_grid(d, l));
+        if (all_stored) {   // training: every level keeps its kernels, no one-workgroup bottom
+            p.km[l] = kStored;
+            continue;
+        }
         if (n <= (size_t)kStoreMaxCells) p.km[l] = kStored;
         else if (precision == NPS_FP64 || l > kMfmaMaxLevel) p.km[l] = kVector;
         else if (precision == NPS_FP32) p.km[l] = kMfmaBf16x3;
@@ -111,9 +120,9 @@ struct Layout {
     size_t total;
 };
 
-Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solve) {
+Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solve, bool all_stored = false) {
     Layout L = {};
-    const Plan p = make_plan(d, levels, precision);
+    const Plan p = make_plan(d, levels, precision, all_stored);
     size_t off = 0;
     auto put = [&](size_t bytes) {
         const size_t at = off;
@@ -147,18 +156,34 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
     return L;
 }
 
-int tile_grid(Grid g) { return std::max(1, tiles_of(g).count()); }
-int red_tile_grid(Grid g) { return red_blocks(tiles_of(g).count()); }
+int tile_grid(Grid g) { return tile_blocks(tiles_of(g).count()); }
+int red_tile_grid(Grid g) { return tile_blocks(tiles_of(g).count()); }
 int red_elem_grid(size_t n) { return red_blocks((int)std::min<size_t>((n + kBlock - 1) / kBlock, 1u << 30)); }
 int elem_grid(size_t n) { return (int)std::min<size_t>(std::max<size_t>((n + kBlock - 1) / kBlock, 1), 65536); }
 
-// Pinned host mirror of the device state, two slots for the one-behind poll.
-State* pinned_state() {
-    thread_local State* p = nullptr;
-    if (!p) {
-        if (hipHostMalloc((void**)&p, 2 * sizeof(State), hipHostMallocDefault) != hipSuccess) p = nullptr;
+// Pinned host memory: a mirror of the device state (read at setup and exit)
+// and the stopping flags the control kernel writes every iteration.
+struct HostMirror {
+    State* state = nullptr;
+    HostFlags* flags = nullptr;     // host address
+    HostFlags* flags_d = nullptr;   // its device address
+};
+
+HostMirror* host_mirror() {
+    thread_local HostMirror m;
+    if (!m.state) {
+        void* p = nullptr;
+        if (hipHostMalloc(&p, sizeof(State) + 256, hipHostMallocMapped) != hipSuccess) return nullptr;
+        m.state = static_cast<State*>(p);
+        m.flags = reinterpret_cast<HostFlags*>(static_cast<char*>(p) + ((sizeof(State) + 63) / 64) * 64);
+        void* d = nullptr;
+        if (hipHostGetDevicePointer(&d, m.flags, 0) != hipSuccess) {
+            m.state = nullptr;
+            return nullptr;
+        }
+        m.flags_d = static_cast<HostFlags*>(d);
     }
-    return p;
+    return &m;
 }
 
 // Optional per-kernel timing: an event pair around every launch.
@@ -349,7 +374,8 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
             }));
         const double b1 = net->aff_b[2 * (l - 1)], b2 = net->aff_b[2 * (l - 1) + 1];
         NPS_TRY(launch("control", 0, s, [&] {
-            k_control<kStageAff><<<1, kCtlBlock, 0, s>>>(st, partials, grid, l - 1, 0, 0, 0, b1, b2, 27.0 * (double)ncells(g));
+            k_control<kStageAff><<<1, kCtlBlock, 0, s>>>(st, partials, grid, l - 1, 0, 0, 0, b1, b2, 27.0 * (double)ncells(g),
+                                                           nullptr);
         }));
     }
     for (int l = 1; l <= L; ++l) {
@@ -450,7 +476,7 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
             constexpr int KM = decltype(km)::value;
             return launch("net_up", (double)ncells(g), s, [&] {
-                k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st);
+                k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st, nullptr);
             });
         }));
     }
@@ -497,60 +523,100 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
         constexpr int KM = decltype(km)::value;
         return launch("net_up_l1", (double)ncells(g), s, [&] {
             k_up_l1<T, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, kst, st, partials, ad[0], ad[1],
-                                                        ad[2], ad[3]);
+                                                        ad[2], ad[3], nullptr);
         });
     });
 }
 
-template <class T, class X>
-int solve_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const double* b, double* x_out,
-               const nps_opts& o, nps_info* info, void* ws, const Plan& plan, const Layout& lay, hipStream_t s) {
-    const Grid g = level_grid(d, 1);
-    const size_t n = ncells(g);
-    State* st = mptr<State>(ws, lay.state);
-    double* partials = mptr<double>(ws, lay.partials);
-    X* x = mptr<X>(ws, lay.x[0]);
-    X* xb1 = mptr<X>(ws, lay.x[1]);
-    T* r = mptr<T>(ws, lay.r);
-    T* dhat = mptr<T>(ws, lay.dhat);
-    const int max_iter = std::max(o.max_iter, 0);
-    State* hs = pinned_state();
-    if (!hs) return fail(NPS_EDEVICE, "hipHostMalloc of the state mirror failed");
-    const double cells = (double)n;
+// One solve in flight, as enqueue steps on one stream: nps_solve drives a
+// single solver to completion; the request server keeps one per slot.
+struct Solver {
+    const nps_net* net = nullptr;
+    const uint8_t* labels = nullptr;
+    const double* b = nullptr;
+    nps_dims d{};
+    nps_opts o{};
+    Plan plan{};
+    Layout lay{};
+    void* ws = nullptr;
+    hipStream_t s = nullptr;
+    State* hs = nullptr;          // pinned host mirror of the device state
+    HostFlags* hf = nullptr;      // pinned flags written by the control kernel
+    HostFlags* hf_d = nullptr;    // device address of hf
+    virtual ~Solver() {}
+    virtual int enqueue_validate() = 0;            // scan, then copy the state to hs
+    virtual int enqueue_setup() = 0;               // pyramid, Aff, stored kernels
+    virtual int enqueue_body(int k) = 0;           // iteration k (see below)
+    virtual int enqueue_finalize(double* x_out) = 0;   // x_out, then copy the state to hs
+};
 
-    NPS_TRY(launch("state_init", 0, s, [&] {
-        k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho);
-    }));
-    const int sgrid = red_elem_grid(n);
-    NPS_TRY(launch("setup_scan", cells, s, [&] { k_scan<X><<<sgrid, kBlock, 0, s>>>(labels, b, n, x, partials); }));
-    NPS_TRY(launch("control", 0, s, [&] {
-        k_control<kStageScan><<<1, kCtlBlock, 0, s>>>(st, partials, sgrid, 0, 0, 0, 0, o.tol, 0.0, 0.0);
-    }));
-    NPS_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
-    NPS_HIP(hipStreamSynchronize(s));
+// Validation verdict from the state mirror after enqueue_validate completed.
+int validation_status(const State* hs) {
     if (hs->bad_label) return fail(NPS_ELABEL, "%d labels outside {0,1,2}", hs->bad_label);
     if (hs->n_fluid == 0) return fail(NPS_ENOFLUID, "no fluid cell");
     if (hs->nonfinite) return fail(NPS_ENONFINITE, "%d non-finite entries of b on fluid cells", hs->nonfinite);
+    return NPS_OK;
+}
+
+// nps_info from the state mirror after enqueue_finalize completed.
+int fill_info(const State* hs, nps_info* info) {
     info->n_fluid = hs->n_fluid;
-    const double bb = hs->bb;
-    if (bb == 0.0) {   // x = 0 solves it exactly
-        NPS_TRY(launch("finalize", cells, s, [&] {
-            k_finalize<X><<<elem_grid(n), kBlock, 0, s>>>(n, labels, x, xb1, st, x_out);
-        }));
-        NPS_HIP(hipStreamSynchronize(s));
+    if (hs->bb == 0.0) {
+        info->iterations = 0;
         info->status = NPS_OK;
+        info->rel_residual = info->rel_residual_rec = 0.0;
+        info->refinements = 0;
         return NPS_OK;
     }
-    NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
+    info->iterations = hs->iter;
+    info->status = hs->done ? hs->status : NPS_NOT_CONVERGED;
+    info->rel_residual = std::sqrt(hs->rr / hs->bb);
+    info->rel_residual_rec = info->rel_residual;
+    info->refinements = hs->iter + 1;
+    if (info->status == NPS_EBREAKDOWN)
+        fail(NPS_EBREAKDOWN, "breakdown: d.Ad <= 0 or not finite at iteration %d", hs->iter + 1);
+    return info->status;
+}
 
-    const int R = o.n_ortho + 1;
-    const int rgrid = red_tile_grid(g);
-    hipEvent_t ev[2];
-    NPS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    NPS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    int result = NPS_OK;
-    // Body k forms x_(k-1) and r_(k-1), then the direction d_k and its step.
-    for (int k = 1; k <= max_iter + 1 && result == NPS_OK; ++k) {
+template <class T, class X>
+struct SolverT : Solver {
+    int enqueue_validate() override {
+        const size_t n = ncells(level_grid(d, 1));
+        State* st = mptr<State>(ws, lay.state);
+        double* partials = mptr<double>(ws, lay.partials);
+        X* x = mptr<X>(ws, lay.x[0]);
+        const int max_iter = std::max(o.max_iter, 0);
+        NPS_TRY(launch("state_init", 0, s, [&] {
+            k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho);
+        }));
+        const int sgrid = red_elem_grid(n);
+        NPS_TRY(launch("setup_scan", (double)n, s, [&] { k_scan<X><<<sgrid, kBlock, 0, s>>>(labels, b, n, x, partials); }));
+        NPS_TRY(launch("control", 0, s, [&] {
+            k_control<kStageScan><<<1, kCtlBlock, 0, s>>>(st, partials, sgrid, 0, 0, 0, 0, o.tol, 0.0, 0.0, nullptr);
+        }));
+        NPS_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
+        return NPS_OK;
+    }
+
+    int enqueue_setup() override {
+        hf->done = 0;
+        hf->iter = 0;
+        return run_setup<T>(net, labels, d, plan, lay, ws, s);
+    }
+
+    // Body k forms x_(k-1) and r_(k-1) = b - A x_(k-1) (applying step k-1),
+    // tests convergence, then forms the direction d_k and its step alpha_k.
+    int enqueue_body(int k) override {
+        const Grid g = level_grid(d, 1);
+        const double cells = (double)ncells(g);
+        State* st = mptr<State>(ws, lay.state);
+        double* partials = mptr<double>(ws, lay.partials);
+        X* x0 = mptr<X>(ws, lay.x[0]);
+        X* x1b = mptr<X>(ws, lay.x[1]);
+        T* r = mptr<T>(ws, lay.r);
+        T* dhat = mptr<T>(ws, lay.dhat);
+        const int R = o.n_ortho + 1;
+        const int rgrid = red_tile_grid(g);
         const int slot = k % R;
         const T* ad[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
         const T* dp[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
@@ -565,52 +631,76 @@ int solve_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const doub
         T* adk = mptr<T>(ws, lay.adring[slot]);
         const T* x2 = nullptr;
         int np = 0;
-        int rc = run_down_l1<T, X, false>(net, labels, d, plan, lay, ws, b, x, xb1, dpend, r, s);
-        if (!rc) rc = launch("control", 0, s, [&] {
-            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, 0, 0, 0, 0, 0.0, 0.0, 0.0);
-        });
-        if (!rc) rc = run_coarse<T>(net, d, plan, lay, ws, s, &x2);
-        if (!rc) rc = run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np);
-        if (!rc && o.n_ortho > 0) rc = launch("control", 0, s, [&] {
-            k_control<kStageDots><<<1, kCtlBlock, 0, s>>>(st, partials, np, sl[0], sl[1], sl[2], sl[3], 0.0, 0.0, 0.0);
-        });
-        if (!rc) rc = launch("ortho_matvec", cells, s, [&] {
+        NPS_TRY((run_down_l1<T, X, false>(net, labels, d, plan, lay, ws, b, x0, x1b, dpend, r, s)));
+        NPS_TRY(launch("control", 0, s, [&] {
+            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+        }));
+        NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
+        NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
+        if (o.n_ortho > 0)
+            NPS_TRY(launch("control", 0, s, [&] {
+                k_control<kStageDots><<<1, kCtlBlock, 0, s>>>(st, partials, np, sl[0], sl[1], sl[2], sl[3], 0.0, 0.0, 0.0,
+                                                               nullptr);
+            }));
+        NPS_TRY(launch("ortho_matvec", cells, s, [&] {
             k_ortho<T><<<rgrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r, dk, adk, st, partials);
-        });
-        if (!rc) rc = launch("control", 0, s, [&] {
-            k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, slot, 0, 0, 0, 0.0, 0.0, 0.0);
-        });
-        if (rc) {
-            result = rc;
-            break;
-        }
-        NPS_HIP(hipMemcpyAsync(&hs[k & 1], st, sizeof(State), hipMemcpyDeviceToHost, s));
-        NPS_HIP(hipEventRecord(ev[k & 1], s));
-        if (k >= 2) {
-            NPS_HIP(hipEventSynchronize(ev[(k - 1) & 1]));
-            if (hs[(k - 1) & 1].done) break;
-        }
+        }));
+        NPS_TRY(launch("control", 0, s, [&] {
+            k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, slot, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+        }));
+        return NPS_OK;
     }
-    if (result == NPS_OK) {
-        result = launch("finalize", cells, s, [&] {
-            k_finalize<X><<<elem_grid(n), kBlock, 0, s>>>(n, labels, x, xb1, st, x_out);
-        });
-    }
-    if (result == NPS_OK) {
+
+    int enqueue_finalize(double* x_out) override {
+        const size_t n = ncells(level_grid(d, 1));
+        State* st = mptr<State>(ws, lay.state);
+        const X* x0 = cptr<X>(ws, lay.x[0]);
+        const X* x1b = cptr<X>(ws, lay.x[1]);
+        NPS_TRY(launch("finalize", (double)n, s, [&] {
+            k_finalize<X><<<elem_grid(n), kBlock, 0, s>>>(n, labels, x0, x1b, st, x_out);
+        }));
         NPS_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
-        NPS_HIP(hipStreamSynchronize(s));
-        info->iterations = hs->iter;
-        info->status = hs->done ? hs->status : NPS_NOT_CONVERGED;
-        info->rel_residual = std::sqrt(hs->rr / bb);
-        info->rel_residual_rec = info->rel_residual;
-        info->refinements = hs->iter + 1;
-        result = info->status;
-        if (result == NPS_EBREAKDOWN)
-            fail(NPS_EBREAKDOWN, "breakdown: d.Ad <= 0 or not finite at iteration %d", hs->iter + 1);
+        return NPS_OK;
     }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    return result;
+};
+
+Solver* make_solver(int precision) {
+    switch (precision) {
+        case NPS_FP64: return new SolverT<double, double>();
+        case NPS_FP32: return new SolverT<float, float>();
+        default: return new SolverT<float, double>();
+    }
+}
+
+// nps_solve: validate, set up, iterate with a one-body-behind poll, finalize.
+int run_solve(Solver& sv, double* x_out, nps_info* info) {
+    NPS_TRY(sv.enqueue_validate());
+    NPS_HIP(hipStreamSynchronize(sv.s));
+    NPS_TRY(validation_status(sv.hs));
+    if (sv.hs->bb != 0.0) {
+        NPS_TRY(sv.enqueue_setup());
+        hipEvent_t ev[2];
+        NPS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+        NPS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        int rc = NPS_OK;
+        const int max_iter = std::max(sv.o.max_iter, 0);
+        volatile HostFlags* hf = sv.hf;
+        for (int k = 1; k <= max_iter + 1 && rc == NPS_OK; ++k) {
+            rc = sv.enqueue_body(k);
+            if (rc) break;
+            if (hipEventRecord(ev[k & 1], sv.s) != hipSuccess) rc = fail(NPS_EDEVICE, "hipEventRecord failed");
+            if (!rc && k >= 2) {   // one body behind: the GPU keeps working while the host waits
+                if (hipEventSynchronize(ev[(k - 1) & 1]) != hipSuccess) rc = fail(NPS_EDEVICE, "hipEventSynchronize failed");
+                if (hf->done) break;
+            }
+        }
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        NPS_TRY(rc);
+    }
+    NPS_TRY(sv.enqueue_finalize(x_out));
+    NPS_HIP(hipStreamSynchronize(sv.s));
+    return fill_info(sv.hs, info);
 }
 
 template <class T>
@@ -625,6 +715,462 @@ int precond_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const T*
     NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
     const T* none[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
     return run_up_l1<T, true>(net, labels, d, plan, lay, ws, x2, d_out, none, s, nullptr);
+}
+
+
+// ---------------------------------------------------------------------------
+// request server
+// ---------------------------------------------------------------------------
+// Pinned host buffers reused by exact size (request grids repeat).
+struct PinnedPool {
+    std::multimap<size_t, void*> free_;
+    void* get(size_t bytes) {
+        auto it = free_.find(bytes);
+        if (it != free_.end()) {
+            void* p = it->second;
+            free_.erase(it);
+            return p;
+        }
+        void* p = nullptr;
+        if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(size_t bytes, void* p) {
+        if (p) free_.emplace(bytes, p);
+    }
+    ~PinnedPool() {
+        for (auto& kv : free_) (void)hipHostFree(kv.second);
+    }
+};
+
+// First-fit allocator over the device arena (offsets, 256-byte granules).
+struct Arena {
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(size_t size) { free_ = {{0, size}}; }
+    bool alloc(size_t bytes, size_t* off) {
+        bytes = align256(bytes);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second < bytes) continue;
+            *off = it->first;
+            const size_t rest = it->second - bytes, at = it->first + bytes;
+            free_.erase(it);
+            if (rest) free_[at] = rest;
+            return true;
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes) {
+        bytes = align256(bytes);
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+    enum Phase { kQueued, kValidating, kRunning, kFinishing, kDone };
+    uint64_t id = 0;
+    nps_dims d{};
+    nps_opts o{};
+    size_t n = 0;
+    uint8_t* lab_h = nullptr;   // pinned copies of the inputs
+    double* b_h = nullptr;
+    double* x_h = nullptr;      // pinned result
+    Phase phase = kQueued;
+    int status = NPS_OK;
+    nps_info info{};
+    Clock::time_point t_submit, t_done;
+    int slot = -1;
+    size_t off = 0, bytes = 0;  // arena region
+    int k = 0;                  // last body enqueued
+};
+
+struct Slot {
+    hipStream_t s = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    State* hs = nullptr;
+    HostFlags* hf = nullptr;
+    HostFlags* hf_d = nullptr;
+    Solver* sv = nullptr;
+    Request* req = nullptr;
+};
+
+struct RequestLayout {
+    size_t ws, lab, b, x, total;
+};
+
+RequestLayout request_layout(nps_dims d, int levels, const nps_opts& o) {
+    RequestLayout r{};
+    const size_t n = ncells(level_grid(d, 1));
+    r.ws = 0;
+    r.lab = align256(make_layout(d, levels, o.precision, o.n_ortho, true).total);
+    r.b = r.lab + align256(n);
+    r.x = r.b + align256(8 * n);
+    r.total = r.x + align256(8 * n);
+    return r;
+}
+
+int check_opts(const nps_opts& o) {
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NPS_EINVAL, "tol must be positive and finite");
+    if (o.max_iter < 0) return fail(NPS_EINVAL, "max_iter must be >= 0");
+    if (o.n_ortho < 0 || o.n_ortho > kMaxOrtho) return fail(NPS_EINVAL, "n_ortho must be in [0, %d]", kMaxOrtho);
+    if (o.precision < NPS_FP64 || o.precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", o.precision);
+    return NPS_OK;
+}
+
+}  // namespace
+
+struct nps_server {
+    const nps_net* net = nullptr;
+    char* arena_d = nullptr;
+    size_t budget = 0;
+    Arena arena;
+    std::vector<Slot> slots;
+    std::deque<Request*> queue;
+    std::unordered_map<uint64_t, Request*> live;   // every request not yet polled
+    uint64_t next_id = 1;
+    PinnedPool pool;
+    void* mirror = nullptr;   // pinned mapped block of the slots' state mirrors and flags
+};
+
+namespace {
+
+void release_inputs(nps_server* srv, Request* r) {
+    srv->pool.put(r->n, r->lab_h);
+    srv->pool.put(8 * r->n, r->b_h);
+    r->lab_h = nullptr;
+    r->b_h = nullptr;
+}
+
+// The request leaves its slot and arena region; its result waits for a poll.
+void retire(nps_server* srv, Slot& sl, int status) {
+    Request* r = sl.req;
+    r->status = status;
+    r->t_done = Clock::now();
+    r->phase = Request::kDone;
+    release_inputs(srv, r);
+    srv->arena.release(r->off, r->bytes);
+    delete sl.sv;
+    sl.sv = nullptr;
+    sl.req = nullptr;
+}
+
+int admit(nps_server* srv, Slot& sl, Request* r) {
+    const RequestLayout rl = request_layout(r->d, srv->net->levels, r->o);
+    char* base = srv->arena_d + r->off;
+    Solver* sv = make_solver(r->o.precision);
+    sv->net = srv->net;
+    sv->labels = reinterpret_cast<const uint8_t*>(base + rl.lab);
+    sv->b = reinterpret_cast<const double*>(base + rl.b);
+    sv->d = r->d;
+    sv->o = r->o;
+    sv->plan = make_plan(r->d, srv->net->levels, r->o.precision);
+    sv->lay = make_layout(r->d, srv->net->levels, r->o.precision, r->o.n_ortho, true);
+    sv->ws = base + rl.ws;
+    sv->s = sl.s;
+    sv->hs = sl.hs;
+    sv->hf = sl.hf;
+    sv->hf_d = sl.hf_d;
+    sl.sv = sv;
+    sl.req = r;
+    r->slot = (int)(&sl - srv->slots.data());
+    NPS_HIP(hipMemcpyAsync(base + rl.lab, r->lab_h, r->n, hipMemcpyHostToDevice, sl.s));
+    NPS_HIP(hipMemcpyAsync(base + rl.b, r->b_h, 8 * r->n, hipMemcpyHostToDevice, sl.s));
+    NPS_TRY(sv->enqueue_validate());
+    NPS_HIP(hipEventRecord(sl.ev[0], sl.s));
+    r->phase = Request::kValidating;
+    return NPS_OK;
+}
+
+int enqueue_finish(nps_server* srv, Slot& sl) {
+    Request* r = sl.req;
+    const RequestLayout rl = request_layout(r->d, srv->net->levels, r->o);
+    double* x_d = reinterpret_cast<double*>(srv->arena_d + r->off + rl.x);
+    NPS_TRY(sl.sv->enqueue_finalize(x_d));
+    NPS_HIP(hipMemcpyAsync(r->x_h, x_d, 8 * r->n, hipMemcpyDeviceToHost, sl.s));
+    NPS_HIP(hipEventRecord(sl.ev[0], sl.s));
+    r->phase = Request::kFinishing;
+    return NPS_OK;
+}
+
+bool event_done(hipEvent_t e) { return hipEventQuery(e) == hipSuccess; }
+
+// Advance one slot without blocking; returns a hard error only for device failures.
+int advance(nps_server* srv, Slot& sl) {
+    Request* r = sl.req;
+    switch (r->phase) {
+        case Request::kValidating: {
+            if (!event_done(sl.ev[0])) return NPS_OK;
+            release_inputs(srv, r);
+            const int v = validation_status(sl.hs);
+            if (v != NPS_OK) {
+                retire(srv, sl, v);
+                return NPS_OK;
+            }
+            if (sl.hs->bb == 0.0) return enqueue_finish(srv, sl);
+            NPS_TRY(sl.sv->enqueue_setup());
+            const int last = std::max(r->o.max_iter, 0) + 1;
+            for (int k = 1; k <= std::min(2, last); ++k) {
+                NPS_TRY(sl.sv->enqueue_body(k));
+                NPS_HIP(hipEventRecord(sl.ev[k & 1], sl.s));
+                r->k = k;
+            }
+            r->phase = Request::kRunning;
+            return NPS_OK;
+        }
+        case Request::kRunning: {
+            const int last = std::max(r->o.max_iter, 0) + 1;
+            const int watch = r->k < last ? r->k - 1 : r->k;   // one behind, or the final body
+            if (watch >= 1 && !event_done(sl.ev[watch & 1])) return NPS_OK;
+            if (watch < 1 && !event_done(sl.ev[r->k & 1])) return NPS_OK;
+            volatile HostFlags* hf = sl.hf;
+            if (hf->done || r->k >= last) return enqueue_finish(srv, sl);
+            r->k += 1;
+            NPS_TRY(sl.sv->enqueue_body(r->k));
+            NPS_HIP(hipEventRecord(sl.ev[r->k & 1], sl.s));
+            return NPS_OK;
+        }
+        case Request::kFinishing: {
+            if (!event_done(sl.ev[0])) return NPS_OK;
+            nps_info info{};
+            const int st = fill_info(sl.hs, &info);
+            r->info = info;
+            retire(srv, sl, st);
+            return NPS_OK;
+        }
+        default:
+            return NPS_OK;
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// training: forward with saved activations, backward, loss
+// ---------------------------------------------------------------------------
+struct TrainLayout {
+    Layout base;                 // state, partials, counts, x1, rb (= down inputs), stored K
+    size_t xup[kMaxLevels + 1], x2[kMaxLevels + 1];
+    size_t gx[kMaxLevels + 1], gx1[kMaxLevels + 1], gr1[kMaxLevels + 1], gr2[kMaxLevels + 1];
+    size_t wpart, spart, dc, res;
+    size_t total;
+};
+
+constexpr int kSumBlocks = 256;   // grid of k_image_sums
+
+TrainLayout make_train_layout(nps_dims d, int levels, int precision) {
+    TrainLayout t = {};
+    t.base = make_layout(d, levels, precision, 0, false, true);
+    size_t off = t.base.total;
+    auto put = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    const size_t s = vec_bytes(precision);
+    for (int l = 1; l <= levels; ++l) {
+        const size_t nl = ncells(level_grid(d, l));
+        if (l >= 2 && l < levels) t.xup[l] = put(s * nl);
+        if (l < levels) {
+            t.x2[l] = put(s * nl);
+            t.gx1[l] = put(s * nl);
+            t.gr2[l] = put(s * nl);
+        }
+        if (l >= 2) {
+            t.gx[l] = put(s * nl);
+            t.gr1[l] = put(s * nl);
+        }
+    }
+    t.wpart = put(sizeof(double) * kWPart * kTrainBlocks);
+    t.spart = put(sizeof(double) * 3 * kTaps * kSumBlocks * levels);
+    t.dc = put(sizeof(double) * 2 * levels);
+    t.res = put(s * ncells(level_grid(d, 1)));
+    t.total = off;
+    return t;
+}
+
+size_t off_c1(int l) { return (size_t)(l - 1) * (27 * 81 + 27); }
+size_t off_c2(int L, int l) { return (size_t)(L + l - 1) * (27 * 81 + 27); }
+size_t off_aff(int L, int l) { return (size_t)(2 * L - 1) * (27 * 81 + 27) + (size_t)(l - 1) * 164; }
+
+template <class T>
+int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws,
+                  const T* r, T* y, hipStream_t s) {
+    const int L = net->levels;
+    const Layout& lay = tl.base;
+    const Plan plan = make_plan(d, L, vec_bytes(NPS_FP32) == sizeof(T) ? NPS_FP32 : NPS_FP64, true);
+    State* st = mptr<State>(ws, lay.state);
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0); }));
+    NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
+    auto img = [&](int l) -> const void* {
+        return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
+    };
+    for (int l = 1; l < L; ++l) {   // image-window sums for the Aff gradients
+        const Grid g = level_grid(d, l);
+        double* sp = mptr<double>(ws, tl.spart) + (size_t)(l - 1) * 3 * kTaps * kSumBlocks;
+        const double inv_full = std::ldexp(1.0, -3 * (l - 1));
+        if (l == 1)
+            NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<true><<<kSumBlocks, kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
+        else
+            NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<false><<<kSumBlocks, kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
+    }
+    NPS_TRY((run_down_l1<T, T, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr, const_cast<T*>(r), s)));
+    for (int l = 2; l <= L; ++l) {
+        const Grid g = level_grid(d, l);
+        const int grid = tile_grid(g);
+        const uint32_t* cnt = cptr<uint32_t>(ws, lay.counts[l]);
+        const T* rin = cptr<T>(ws, lay.rb[l]);
+        T* x1 = mptr<T>(ws, lay.x1[l]);
+        T* rnext = l < L ? mptr<T>(ws, lay.rb[l + 1]) : nullptr;
+        const T* kst = cptr<T>(ws, lay.k1[l]);
+        const CConvW<T>* w = cconv_block<T>(net, block_down(l));
+        if (l < L)
+            NPS_TRY(launch("net_down", (double)ncells(g), s, [&] {
+                k_down<T, kStored, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, nullptr, kst, st);
+            }));
+        else
+            NPS_TRY(launch("net_coarsest", (double)ncells(g), s, [&] {
+                k_down<T, kStored, false><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, nullptr, w, nullptr, kst, st);
+            }));
+    }
+    auto x_of = [&](int l) -> const T* { return l == L ? cptr<T>(ws, lay.x1[L]) : cptr<T>(ws, tl.xup[l]); };
+    for (int l = L - 1; l >= 2; --l) {
+        const Grid g = level_grid(d, l);
+        const int grid = tile_grid(g);
+        const uint32_t* cnt = cptr<uint32_t>(ws, lay.counts[l]);
+        const T* xc = x_of(l + 1);
+        const T* x1 = cptr<T>(ws, lay.x1[l]);
+        T* xo = mptr<T>(ws, tl.xup[l]);
+        T* x2o = mptr<T>(ws, tl.x2[l]);
+        const T* kst = cptr<T>(ws, lay.k2[l]);
+        const CConvW<T>* w = cconv_block<T>(net, block_up(net, l));
+        NPS_TRY(launch("net_up", (double)ncells(g), s, [&] {
+            k_up<T, kStored><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, nullptr, kst, l - 1, st, x2o);
+        }));
+    }
+    {
+        const Grid g = level_grid(d, 1);
+        const int grid = tile_grid(g);
+        const T* xc = x_of(2);
+        const T* x1 = cptr<T>(ws, lay.x1[1]);
+        T* x2o = mptr<T>(ws, tl.x2[1]);
+        const T* kst = cptr<T>(ws, lay.k2[1]);
+        const CConvW<T>* w = cconv_block<T>(net, block_up(net, 1));
+        double* partials = mptr<double>(ws, lay.partials);
+        NPS_TRY(launch("net_up_l1", (double)ncells(g), s, [&] {
+            k_up_l1<T, kStored, true><<<grid, kBlock, 0, s>>>(labels, g, xc, x1, y, w, nullptr, kst, st, partials, nullptr,
+                                                            nullptr, nullptr, nullptr, x2o);
+        }));
+    }
+    return NPS_OK;
+}
+
+template <class T>
+int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws,
+                   const T* r, const T* gy, double* grad, hipStream_t s) {
+    const int L = net->levels;
+    const Layout& lay = tl.base;
+    State* st = mptr<State>(ws, lay.state);
+    double* wpart = mptr<double>(ws, tl.wpart);
+    double* dc = mptr<double>(ws, tl.dc);
+    auto img = [&](int l) -> const void* {
+        return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
+    };
+    auto x_of = [&](int l) -> const T* { return l == L ? cptr<T>(ws, lay.x1[L]) : cptr<T>(ws, tl.xup[l]); };
+    // up sweep, reversed
+    for (int l = 1; l < L; ++l) {
+        const Grid g = level_grid(d, l);
+        const int grid = std::min(tile_grid(g), kTrainBlocks);
+        const T* gin = l == 1 ? gy : cptr<T>(ws, tl.gx[l]);
+        const T* xc = x_of(l + 1);
+        const T* x1 = cptr<T>(ws, lay.x1[l]);
+        const T* x2 = cptr<T>(ws, tl.x2[l]);
+        const T* k2 = cptr<T>(ws, lay.k2[l]);
+        T* gx1 = mptr<T>(ws, tl.gx1[l]);
+        T* gr2 = mptr<T>(ws, tl.gr2[l]);
+        if (l == 1)
+            NPS_TRY(launch("train_bwd_up", (double)ncells(g), s, [&] {
+                k_bwd_up<T, true><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
+            }));
+        else
+            NPS_TRY(launch("train_bwd_up", (double)ncells(g), s, [&] {
+                k_bwd_up<T, false><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
+            }));
+        const double scale = std::ldexp(1.0, -3 * (l - 1));
+        double* gW = grad + off_c2(L, l);
+        double* dcl = dc + 2 * (l - 1);
+        NPS_TRY(launch("train_wgrad_reduce", 0, s, [&] {
+            k_wgrad_reduce<<<1, kBlock, 0, s>>>(wpart, grid, scale, gW, gW + 27 * 81, dcl);
+        }));
+        const double* sp = cptr<double>(ws, tl.spart) + (size_t)(l - 1) * 3 * kTaps * kSumBlocks;
+        double* ga = grad + off_aff(L, l);
+        const double n27 = 27.0 * (double)ncells(g);
+        NPS_TRY(launch("train_aff_grad", 0, s, [&] { k_aff_grad<<<1, 128, 0, s>>>(sp, kSumBlocks, dcl, n27, ga, ga + 82); }));
+        const Grid gc = level_grid(d, l + 1);
+        T* gxc = mptr<T>(ws, tl.gx[l + 1]);
+        NPS_TRY(launch("train_bwd_interp", (double)ncells(gc), s, [&] {
+            k_bwd_interp<T><<<elem_grid(ncells(gc)), kBlock, 0, s>>>(gc, gr2, gxc);
+        }));
+    }
+    // down sweep, reversed (the coarsest level's output gradient is gx^L)
+    for (int l = L; l >= 1; --l) {
+        const Grid g = level_grid(d, l);
+        const int grid = std::min(tile_grid(g), kTrainBlocks);
+        const T* gx1 = l == L ? cptr<T>(ws, tl.gx[L]) : cptr<T>(ws, tl.gx1[l]);
+        const T* gr_next = l < L ? cptr<T>(ws, tl.gr1[l + 1]) : nullptr;
+        const T* r1 = l == 1 ? r : cptr<T>(ws, lay.rb[l]);
+        const T* k1 = cptr<T>(ws, lay.k1[l]);
+        T* gr1 = l > 1 ? mptr<T>(ws, tl.gr1[l]) : nullptr;
+        if (l == 1)
+            NPS_TRY(launch("train_bwd_down", (double)ncells(g), s, [&] {
+                k_bwd_down<T, true><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
+            }));
+        else
+            NPS_TRY(launch("train_bwd_down", (double)ncells(g), s, [&] {
+                k_bwd_down<T, false><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
+            }));
+        const double scale = std::ldexp(1.0, -3 * (l - 1));
+        double* gW = grad + off_c1(l);
+        NPS_TRY(launch("train_wgrad_reduce", 0, s, [&] {
+            k_wgrad_reduce<<<1, kBlock, 0, s>>>(wpart, grid, scale, gW, gW + 27 * 81, nullptr);
+        }));
+    }
+    (void)st;
+    return NPS_OK;
+}
+
+template <class T>
+int train_loss(const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws, const T* b, const T* y, T* gy,
+               double* loss_h, hipStream_t s) {
+    const Layout& lay = tl.base;
+    const Grid g = level_grid(d, 1);
+    State* st = mptr<State>(ws, lay.state);
+    double* partials = mptr<double>(ws, lay.partials);
+    T* res = mptr<T>(ws, tl.res);
+    const int grid = tile_grid(g);
+    NPS_TRY(launch("train_residual", (double)ncells(g), s, [&] {
+        k_train_residual<T><<<grid, kBlock, 0, s>>>(labels, g, b, y, res, partials);
+    }));
+    NPS_TRY(launch("control", 0, s, [&] {
+        k_control<kStageLoss><<<1, kCtlBlock, 0, s>>>(st, partials, grid, 0, 0, 0, 0, 0.0, 0.0, 0.0, nullptr);
+    }));
+    NPS_TRY(launch("train_gy", (double)ncells(g), s, [&] { k_train_gy<T><<<grid, kBlock, 0, s>>>(labels, g, res, st, gy); }));
+    double rr = 0.0;
+    NPS_HIP(hipMemcpyAsync(&rr, &st->rr, sizeof(double), hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipStreamSynchronize(s));
+    *loss_h = std::sqrt(rr);
+    return NPS_OK;
 }
 
 }  // namespace
@@ -735,12 +1281,24 @@ int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const 
     if (ws_bytes < lay.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
     if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
     std::memset(info, 0, sizeof(*info));
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    switch (o.precision) {
-        case NPS_FP64: return solve_impl<double, double>(net, labels_d, dims, b_d, x_d, o, info, ws_d, plan, lay, s);
-        case NPS_FP32: return solve_impl<float, float>(net, labels_d, dims, b_d, x_d, o, info, ws_d, plan, lay, s);
-        default: return solve_impl<float, double>(net, labels_d, dims, b_d, x_d, o, info, ws_d, plan, lay, s);
-    }
+    HostMirror* hm = host_mirror();
+    if (!hm) return fail(NPS_EDEVICE, "hipHostMalloc of the host mirror failed");
+    Solver* sv = make_solver(o.precision);
+    sv->net = net;
+    sv->labels = labels_d;
+    sv->b = b_d;
+    sv->d = dims;
+    sv->o = o;
+    sv->plan = plan;
+    sv->lay = lay;
+    sv->ws = ws_d;
+    sv->s = static_cast<hipStream_t>(stream);
+    sv->hs = hm->state;
+    sv->hf = hm->flags;
+    sv->hf_d = hm->flags_d;
+    const int rc = run_solve(*sv, x_d, info);
+    delete sv;
+    return rc;
 }
 
 int nps_apply_laplacian(const uint8_t* labels_d, nps_dims dims, const void* x_d, void* y_d, int precision,
@@ -779,6 +1337,57 @@ int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims
                                     ws_d, plan, lay, s);
     return precond_impl<float>(net, labels_d, dims, static_cast<const float*>(r_d), static_cast<float*>(d_d), ws_d,
                                plan, lay, s);
+}
+
+
+size_t nps_train_workspace_bytes(nps_dims dims, int levels, int precision) {
+    if (check_dims(dims, levels) != NPS_OK) return 0;
+    if (precision != NPS_FP64 && precision != NPS_FP32) return 0;
+    return make_train_layout(dims, levels, precision).total;
+}
+
+int nps_net_forward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, void* y_d,
+                    int precision, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!net || !labels_d || !r_d || !y_d || !ws_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "training precision must be FP64 or FP32");
+    const TrainLayout tl = make_train_layout(dims, net->levels, precision);
+    if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == NPS_FP64)
+        return train_forward<double>(net, labels_d, dims, tl, ws_d, static_cast<const double*>(r_d), static_cast<double*>(y_d), s);
+    return train_forward<float>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(r_d), static_cast<float*>(y_d), s);
+}
+
+int nps_net_backward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, const void* gy_d,
+                     double* grad_d, int precision, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!net || !labels_d || !r_d || !gy_d || !grad_d || !ws_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "training precision must be FP64 or FP32");
+    const TrainLayout tl = make_train_layout(dims, net->levels, precision);
+    if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == NPS_FP64)
+        return train_backward<double>(net, labels_d, dims, tl, ws_d, static_cast<const double*>(r_d),
+                                      static_cast<const double*>(gy_d), grad_d, s);
+    return train_backward<float>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(r_d),
+                                 static_cast<const float*>(gy_d), grad_d, s);
+}
+
+int nps_train_loss(const uint8_t* labels_d, nps_dims dims, int levels, const void* b_d, const void* y_d, void* gy_d,
+                   double* loss_h, int precision, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!labels_d || !b_d || !y_d || !gy_d || !loss_h || !ws_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, levels));
+    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "training precision must be FP64 or FP32");
+    const TrainLayout tl = make_train_layout(dims, levels, precision);
+    if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == NPS_FP64)
+        return train_loss<double>(labels_d, dims, tl, ws_d, static_cast<const double*>(b_d), static_cast<const double*>(y_d),
+                                  static_cast<double*>(gy_d), loss_h, s);
+    return train_loss<float>(labels_d, dims, tl, ws_d, static_cast<const float*>(b_d), static_cast<const float*>(y_d),
+                             static_cast<float*>(gy_d), loss_h, s);
 }
 
 int nps_profile_enable(int on) {
@@ -821,6 +1430,145 @@ int nps_profile_read(nps_kernel_stat* out_h, int max_records, int* n_records) {
     if (rc) return rc;
     if (overflow) return fail(NPS_ENOMEM, "more than %zu timing events; later launches were not recorded", kMaxProfEvents / 2);
     return NPS_OK;
+}
+
+
+int nps_server_create(const nps_net* net, size_t hbm_budget, int max_slots, nps_server** out) {
+    if (!net || !out) return fail(NPS_EINVAL, "null argument");
+    if (max_slots < 1 || max_slots > 64) return fail(NPS_EINVAL, "max_slots must be in [1, 64]");
+    if (hbm_budget < (1u << 20)) return fail(NPS_EINVAL, "hbm_budget too small");
+    nps_server* srv = new nps_server();
+    srv->net = net;
+    srv->budget = align256(hbm_budget);
+    if (hipMalloc((void**)&srv->arena_d, srv->budget) != hipSuccess) {
+        delete srv;
+        return fail(NPS_ENOMEM, "cannot allocate a %zu-byte arena", hbm_budget);
+    }
+    srv->arena.init(srv->budget);
+    const size_t per = ((sizeof(State) + sizeof(HostFlags) + 255) / 256) * 256;
+    if (hipHostMalloc(&srv->mirror, per * max_slots, hipHostMallocMapped) != hipSuccess) {
+        (void)hipFree(srv->arena_d);
+        delete srv;
+        return fail(NPS_EDEVICE, "hipHostMalloc of the slot mirrors failed");
+    }
+    srv->slots.resize(max_slots);
+    for (int i = 0; i < max_slots; ++i) {
+        Slot& sl = srv->slots[i];
+        char* m = static_cast<char*>(srv->mirror) + per * i;
+        sl.hs = reinterpret_cast<State*>(m);
+        sl.hf = reinterpret_cast<HostFlags*>(m + sizeof(State));
+        void* d = nullptr;
+        bool ok = hipHostGetDevicePointer(&d, sl.hf, 0) == hipSuccess;
+        sl.hf_d = static_cast<HostFlags*>(d);
+        ok = ok && hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.ev[0], hipEventDisableTiming) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&sl.ev[1], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            nps_server_destroy(srv);
+            return fail(NPS_EDEVICE, "stream/event creation failed");
+        }
+    }
+    *out = srv;
+    return NPS_OK;
+}
+
+void nps_server_destroy(nps_server* srv) {
+    if (!srv) return;
+    for (Slot& sl : srv->slots) {
+        if (sl.s) (void)hipStreamSynchronize(sl.s);
+        delete sl.sv;
+        if (sl.ev[0]) (void)hipEventDestroy(sl.ev[0]);
+        if (sl.ev[1]) (void)hipEventDestroy(sl.ev[1]);
+        if (sl.s) (void)hipStreamDestroy(sl.s);
+    }
+    for (auto& kv : srv->live) {
+        Request* r = kv.second;
+        srv->pool.put(r->n, r->lab_h);
+        srv->pool.put(8 * r->n, r->b_h);
+        srv->pool.put(8 * r->n, r->x_h);
+        delete r;
+    }
+    if (srv->arena_d) (void)hipFree(srv->arena_d);
+    if (srv->mirror) (void)hipHostFree(srv->mirror);
+    delete srv;
+}
+
+size_t nps_server_request_bytes(const nps_server* srv, nps_dims dims, const nps_opts* opts) {
+    if (!srv || !opts || check_dims(dims, srv->net->levels) != NPS_OK || check_opts(*opts) != NPS_OK) return 0;
+    return request_layout(dims, srv->net->levels, *opts).total;
+}
+
+int nps_server_submit(nps_server* srv, const uint8_t* labels_h, nps_dims dims, const double* b_h,
+                      const nps_opts* opts, uint64_t* req_id) {
+    if (!srv || !labels_h || !b_h || !opts || !req_id) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, srv->net->levels));
+    NPS_TRY(check_opts(*opts));
+    const size_t bytes = request_layout(dims, srv->net->levels, *opts).total;
+    if (bytes > srv->budget) return fail(NPS_ENOMEM, "request needs %zu bytes, the arena has %zu", bytes, srv->budget);
+    Request* r = new Request();
+    r->id = srv->next_id++;
+    r->d = dims;
+    r->o = *opts;
+    r->n = ncells(level_grid(dims, 1));
+    r->bytes = bytes;
+    r->lab_h = static_cast<uint8_t*>(srv->pool.get(r->n));
+    r->b_h = static_cast<double*>(srv->pool.get(8 * r->n));
+    r->x_h = static_cast<double*>(srv->pool.get(8 * r->n));
+    if (!r->lab_h || !r->b_h || !r->x_h) {
+        srv->pool.put(r->n, r->lab_h);
+        srv->pool.put(8 * r->n, r->b_h);
+        srv->pool.put(8 * r->n, r->x_h);
+        delete r;
+        return fail(NPS_EDEVICE, "pinned host allocation failed");
+    }
+    std::memcpy(r->lab_h, labels_h, r->n);
+    std::memcpy(r->b_h, b_h, 8 * r->n);
+    r->t_submit = Clock::now();
+    srv->queue.push_back(r);
+    srv->live[r->id] = r;
+    *req_id = r->id;
+    return NPS_OK;
+}
+
+int nps_server_step(nps_server* srv, int* n_active, int* n_queued) {
+    if (!srv) return fail(NPS_EINVAL, "null argument");
+    for (Slot& sl : srv->slots)
+        if (sl.req) NPS_TRY(advance(srv, sl));
+    // admission, first in first out, while a slot and arena space are free
+    while (!srv->queue.empty()) {
+        Request* r = srv->queue.front();
+        Slot* free_slot = nullptr;
+        for (Slot& sl : srv->slots)
+            if (!sl.req) {
+                free_slot = &sl;
+                break;
+            }
+        if (!free_slot || !srv->arena.alloc(r->bytes, &r->off)) break;
+        srv->queue.pop_front();
+        NPS_TRY(admit(srv, *free_slot, r));
+    }
+    int active = 0;
+    for (Slot& sl : srv->slots) active += sl.req != nullptr;
+    if (n_active) *n_active = active;
+    if (n_queued) *n_queued = (int)srv->queue.size();
+    return NPS_OK;
+}
+
+int nps_server_poll(nps_server* srv, uint64_t req_id, double* x_h, nps_info* info, double* latency_ms) {
+    if (!srv) return fail(NPS_EINVAL, "null argument");
+    auto it = srv->live.find(req_id);
+    if (it == srv->live.end()) return fail(NPS_EINVAL, "unknown request %llu", (unsigned long long)req_id);
+    Request* r = it->second;
+    if (r->phase != Request::kDone) return NPS_PENDING;
+    if (x_h) std::memcpy(x_h, r->x_h, 8 * r->n);
+    if (info) *info = r->info;
+    if (info) info->status = r->status;
+    if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();
+    const int st = r->status;
+    srv->pool.put(8 * r->n, r->x_h);
+    srv->live.erase(it);
+    delete r;
+    return st;
 }
 
 const char* nps_last_error(void) { return g_err.c_str(); }

@@ -18,9 +18,10 @@ constexpr int kMaxOrtho = 4;
 constexpr int kRing = kMaxOrtho + 1;
 constexpr int kTaps = 27;
 constexpr int kRedWidth = 4;          // doubles reduced per block at most
-constexpr int kMaxRedBlocks = 1024;   // cap on blocks of reducing kernels
+constexpr int kMaxRedBlocks = 16384;  // cap on blocks of reducing kernels (partials per value)
+constexpr int kXcds = 8;              // accelerator dies; workgroups are dealt to them round-robin
 constexpr int kBlock = 256;           // threads per block of the stencil kernels
-constexpr int kCtlBlock = 256;        // threads of the control kernel
+constexpr int kCtlBlock = 1024;       // threads of the control kernel
 constexpr int kStoreMaxCells = 32768; // levels at most this large keep their kernels K in HBM
 constexpr int kBottomMaxCells = 512;  // levels at most this large run in one workgroup
 constexpr int kMfmaMaxLevel = 3;      // counts <= 64: exact in bf16 and fp16
@@ -111,11 +112,26 @@ __host__ __device__ inline Tiles tiles_of(Grid g) {
     return Tiles{(g.nx + TX - 1) / TX, (g.ny + TY - 1) / TY, (g.nz + TZ - 1) / TZ};
 }
 
+// Grid of a tile kernel: one block per tile up to kMaxRedBlocks, rounded up
+// to a multiple of kXcds so that every die owns an equal, contiguous range of
+// tiles (see tile_span).
+inline int tile_blocks(int tiles) {
+    int g = tiles < 1 ? 1 : tiles;
+    if (g > kXcds) g = (g + kXcds - 1) / kXcds * kXcds;
+    return g < kMaxRedBlocks ? g : kMaxRedBlocks;
+}
+
 inline int red_blocks(int work_blocks) {
     return work_blocks < kMaxRedBlocks ? (work_blocks > 0 ? work_blocks : 1) : kMaxRedBlocks;
 }
 
+// Host-visible copy of the stopping decision, written by the control kernel.
+struct HostFlags {
+    int done;
+    int iter;
+};
+
 // Control-kernel stages.
-enum Stage : int { kStageScan = 0, kStageAff = 1, kStageResidual = 2, kStageDots = 3, kStageStep = 4 };
+enum Stage : int { kStageScan = 0, kStageAff = 1, kStageResidual = 2, kStageDots = 3, kStageStep = 4, kStageLoss = 5 };
 
 }  // namespace nps

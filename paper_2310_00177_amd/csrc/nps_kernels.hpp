@@ -19,6 +19,8 @@
 // partial per block, and the one-block control kernel that follows sums them
 // in block order (deterministic) and updates the solver state.  Kernel
 // boundaries provide the cross-XCD visibility.
+#pragma once
+
 #include "nps_internal.hpp"
 
 #include <cmath>
@@ -39,7 +41,7 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Block sum of kRedWidth values, written by thread 0 to partials[blockIdx.x].
+// Block sum of kRedWidth values; value w of block b goes to partials[w * kMaxRedBlocks + b].
 template <int NT>
 __device__ inline void block_partials(double (&v)[kRedWidth], double* partials) {
     __shared__ double sh[kRedWidth][NT / 64];
@@ -56,7 +58,7 @@ __device__ inline void block_partials(double (&v)[kRedWidth], double* partials) 
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < NT / 64; ++i) s += sh[threadIdx.x][i];
-        partials[(size_t)blockIdx.x * kRedWidth + threadIdx.x] = s;
+        partials[(size_t)threadIdx.x * kMaxRedBlocks + blockIdx.x] = s;
     }
 }
 
@@ -66,6 +68,22 @@ __device__ inline void block_partials(double (&v)[kRedWidth], double* partials) 
 struct TileOrigin {
     int x0, y0, z0;
 };
+
+// The tiles a block processes: [t0, t1) with stride `step`.  When the grid
+// is a multiple of kXcds, die x (blocks b with b % kXcds == x) owns the x-th
+// contiguous eighth of the tiles in x-fastest order, so tiles that share
+// halos are staged through the same L2.
+struct TileSpan {
+    int t0, t1, step;
+};
+
+__device__ inline TileSpan tile_span(int ntiles) {
+    const int G = gridDim.x, b = blockIdx.x;
+    if (G % kXcds != 0) return TileSpan{b, ntiles, G};
+    const int chunk = (ntiles + kXcds - 1) / kXcds;
+    const int x = b % kXcds;
+    return TileSpan{x * chunk + b / kXcds, min((x + 1) * chunk, ntiles), G / kXcds};
+}
 
 __device__ inline TileOrigin tile_origin(int tile, Tiles tl) {
     TileOrigin o;
@@ -433,45 +451,50 @@ __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ 
 // ---------------------------------------------------------------------------
 // the one-block control kernel
 // ---------------------------------------------------------------------------
-// Sums nparts partials of kRedWidth doubles in block order and updates the
-// state for one stage of the iteration.
+// Sums nparts per-block partials (structure of arrays, block order: a fixed
+// summation order) and updates the state for one stage of the iteration.
+// The stopping decision is mirrored to host memory (hf) for the host loop.
 template <int STAGE>
 __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* __restrict__ partials, int nparts,
                                                        int i0, int i1, int i2, int i3, double d0, double d1,
-                                                       double d2) {
+                                                       double d2, HostFlags* hf) {
     if ((STAGE == kStageResidual || STAGE == kStageDots || STAGE == kStageStep) && st->done) return;
-    __shared__ double sh[kRedWidth][kCtlBlock / 64];
-    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    constexpr int W = STAGE == kStageScan ? 4 : STAGE == kStageAff ? 2 : STAGE == kStageResidual ? 1
+                    : STAGE == kStageDots ? kMaxOrtho : STAGE == kStageLoss ? 1 : 2;
+    __shared__ double sh[W][kCtlBlock / 64];
+    double v[W];
+#pragma unroll
+    for (int w = 0; w < W; ++w) v[w] = 0.0;
     for (int b = threadIdx.x; b < nparts; b += kCtlBlock) {
 #pragma unroll
-        for (int w = 0; w < kRedWidth; ++w) v[w] += partials[(size_t)b * kRedWidth + w];
+        for (int w = 0; w < W; ++w) v[w] += partials[(size_t)w * kMaxRedBlocks + b];
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-    for (int w = 0; w < kRedWidth; ++w) v[w] = wave_sum(v[w]);
+    for (int w = 0; w < W; ++w) v[w] = wave_sum(v[w]);
     if (lane == 0) {
 #pragma unroll
-        for (int w = 0; w < kRedWidth; ++w) sh[w][wid] = v[w];
+        for (int w = 0; w < W; ++w) sh[w][wid] = v[w];
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
 #pragma unroll
-    for (int w = 0; w < kRedWidth; ++w) {
+    for (int w = 0; w < W; ++w) {
         double s = 0.0;
 #pragma unroll
         for (int i = 0; i < kCtlBlock / 64; ++i) s += sh[w][i];
         v[w] = s;
     }
-    if (STAGE == kStageScan) {            // d0 = tol
+    if constexpr (STAGE == kStageScan) {            // d0 = tol
         st->bb = v[0];
         st->n_fluid = (int)v[1];
         st->bad_label = (int)v[2];
         st->nonfinite = (int)v[3];
         st->tol2bb = d0 * d0 * v[0];
-    } else if (STAGE == kStageAff) {      // i0 = level index, d0/d1 = Aff biases, d2 = 27 n_l
+    } else if constexpr (STAGE == kStageAff) {      // i0 = level index, d0/d1 = Aff biases, d2 = 27 n_l
         st->c1[i0] = d0 + v[0] / d2;
         st->c2[i0] = d1 + v[1] / d2;
-    } else if (STAGE == kStageResidual) { // ||b - A x_k||^2 of the iterate down_l1 just formed
+    } else if constexpr (STAGE == kStageResidual) { // ||b - A x_k||^2 of the iterate down_l1 just formed
         const double rr = v[0];
         const int iter = st->iter + (st->pending ? 1 : 0);
         st->iter = iter;
@@ -490,16 +513,23 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
             st->done = 1;
             st->status = st->fixed ? 0 : 1;   // NPS_OK / NPS_NOT_CONVERGED
         }
-    } else if (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
+        if (hf) {
+            hf->iter = iter;
+            hf->done = st->done;
+        }
+    } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
         const int sl[kMaxOrtho] = {i0, i1, i2, i3};
         for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
-    } else if (STAGE == kStageStep) {     // i0: ring slot of the new direction
+    } else if constexpr (STAGE == kStageLoss) {     // training loss: ||b - A y||^2
+        st->rr = v[0];
+    } else if constexpr (STAGE == kStageStep) {     // i0: ring slot of the new direction
         const double dAd = v[0], rd = v[1];
         st->dAd[i0] = dAd;
         st->rd = rd;
         if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) {
             st->done = 1;
             st->status = -6;   // NPS_EBREAKDOWN
+            if (hf) hf->done = 1;
         } else {
             st->alpha = rd / dAd;
             st->pending = 1;
@@ -558,7 +588,8 @@ __global__ __launch_bounds__(kBlock) void k_down_l1(
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         stage_image<true>(img_s, lab, g, o);
@@ -633,7 +664,8 @@ __global__ __launch_bounds__(kBlock) void k_down(const uint32_t* __restrict__ cn
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
-    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         stage_image<false>(img_s, cnt, g, o);
@@ -679,14 +711,41 @@ __device__ inline T interp_at(const T* __restrict__ xc, Grid gc, int z, int y, i
 }
 
 // Stage Interp(xc) over the haloed tile (zero outside the level's grid: the
-// zero padding of the CConv input).
+// zero padding of the CConv input).  The coarse cells the tile needs, a
+// CX x CY x CZ block starting two coarse cells before the tile, are first
+// staged in LDS with their coordinates clamped into the coarse grid, which is
+// exactly the interpolation's edge rule, so the fine values are formed from
+// LDS without further clamping.
+constexpr int CXS = TX / 2 + 4, CYS = TY / 2 + 4, CZS = TZ / 2 + 4;
+constexpr int kCoarseTile = CXS * CYS * CZS;
+
 template <class T>
-__device__ inline void stage_interp(T* r_s, const T* __restrict__ xc, Grid g, TileOrigin o) {
+__device__ inline void stage_interp(T* r_s, T* c_s, const T* __restrict__ xc, Grid g, TileOrigin o) {
     const Grid gc = coarser(g);
+    const int bx = o.x0 / 2 - 2, by = o.y0 / 2 - 2, bz = o.z0 / 2 - 2;
+    for (int i = threadIdx.x; i < kCoarseTile; i += kBlock) {
+        const int cx = i % CXS, cy = (i / CXS) % CYS, cz = i / (CXS * CYS);
+        const int jx = min(max(bx + cx, 0), gc.nx - 1), jy = min(max(by + cy, 0), gc.ny - 1),
+                  jz = min(max(bz + cz, 0), gc.nz - 1);
+        c_s[i] = xc[cell_index(gc, jz, jy, jx)];
+    }
+    __syncthreads();
+    const T a = T(0.75), b = T(0.25);
     for (int i = threadIdx.x; i < kHalo; i += kBlock) {
         const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
-        r_s[i] = in_grid(g, zz, yy, xx) ? interp_at<T>(xc, gc, zz, yy, xx) : T(0);
+        const int x = o.x0 + hx - 1, y = o.y0 + hy - 1, z = o.z0 + hz - 1;
+        T v = T(0);
+        if (in_grid(g, z, y, x)) {
+            const int jx = (x >> 1) - bx, jy = (y >> 1) - by, jz = (z >> 1) - bz;
+            const int nx = jx + ((x & 1) ? 1 : -1), ny = jy + ((y & 1) ? 1 : -1), nz = jz + ((z & 1) ? 1 : -1);
+            auto at = [&](int zz, int yy, int xx) { return c_s[(zz * CYS + yy) * CXS + xx]; };
+            const T p00 = a * at(jz, jy, jx) + b * at(jz, jy, nx);
+            const T p01 = a * at(jz, ny, jx) + b * at(jz, ny, nx);
+            const T p10 = a * at(nz, jy, jx) + b * at(nz, jy, nx);
+            const T p11 = a * at(nz, ny, jx) + b * at(nz, ny, nx);
+            v = a * (a * p00 + b * p01) + b * (a * p10 + b * p11);
+        }
+        r_s[i] = v;
     }
 }
 
@@ -696,20 +755,22 @@ __global__ __launch_bounds__(kBlock) void k_up(const uint32_t* __restrict__ cnt,
                                                const T* __restrict__ xc, const T* __restrict__ x1,
                                                T* __restrict__ xout, const CConvW<T>* __restrict__ w,
                                                const MfmaW* __restrict__ wm, const T* __restrict__ kst, int lvl,
-                                               const State* st) {
+                                               const State* st, T* __restrict__ x2out) {
     if (st->done) return;
     __shared__ uint32_t img_s[kHalo];
     __shared__ T r_s[kHalo];
+    __shared__ T c_s[kCoarseTile];
     const T c1 = (T)st->c1[lvl], c2 = (T)st->c2[lvl];
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
-    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         stage_image<false>(img_s, cnt, g, o);
-        stage_interp<T>(r_s, xc, g, o);
+        stage_interp<T>(r_s, c_s, xc, g, o);
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
@@ -717,6 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_up(const uint32_t* __restrict__ cnt,
         const int mode = KM == kStored ? -1 : choose_mode<false>(active, img_s, base, full, false, false);
         const T x2 = cconv_any<T, KM, false>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
         if (active) xout[idx] = c1 * x1[idx] + c2 * x2;
+        if (active && x2out) x2out[idx] = x2;
     }
 }
 
@@ -728,10 +790,11 @@ __global__ __launch_bounds__(kBlock) void k_up_l1(
     const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ xc, const T* __restrict__ x1,
     T* __restrict__ dhat, const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
     const T* __restrict__ kst, const State* st, double* partials, const T* __restrict__ ad0,
-    const T* __restrict__ ad1, const T* __restrict__ ad2, const T* __restrict__ ad3) {
+    const T* __restrict__ ad1, const T* __restrict__ ad2, const T* __restrict__ ad3, T* __restrict__ x2out) {
     if (!HOOK && st->done) return;
     __shared__ uint32_t img_s[kHalo];
     __shared__ T r_s[kHalo];
+    __shared__ T c_s[kCoarseTile];
     const T c1 = (T)st->c1[0], c2 = (T)st->c2[0];
     const T scale = HOOK ? T(1) : (T)st->scale;
     const int nprev = HOOK ? 0 : st->nprev;
@@ -740,11 +803,12 @@ __global__ __launch_bounds__(kBlock) void k_up_l1(
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         stage_image<true>(img_s, lab, g, o);
-        stage_interp<T>(r_s, xc, g, o);
+        stage_interp<T>(r_s, c_s, xc, g, o);
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
@@ -755,6 +819,7 @@ __global__ __launch_bounds__(kBlock) void k_up_l1(
             T out = T(0);
             if (img_s[base] == (uint32_t)kFluid) out = (c1 * x1[idx] + c2 * x2) * scale;
             dhat[idx] = out;
+            if (x2out) x2out[idx] = x2;
             if (!HOOK) {
                 if (nprev > 0) v[0] += (double)out * (double)ad0[idx];
                 if (nprev > 1) v[1] += (double)out * (double)ad1[idx];
@@ -779,7 +844,7 @@ struct BottomArgs {
     T* xout;
 };
 
-constexpr int kBottomThreads = 256;
+constexpr int kBottomThreads = 512;
 constexpr int kBottomLds = 2 * 640;   // >= 2 * sum of the bottom levels' cells
 
 template <class T>
@@ -811,9 +876,11 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
         const int nl = (int)ncells(g);
         for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
             const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+            const T* __restrict__ k1 = a.k1[l];
             T acc = T(0);
+#pragma unroll
             for (int t = 0; t < kTaps; ++t)
-                acc = fma(a.k1[l][(size_t)t * nl + p], bottom_get(rb[l], g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+                acc = fma(k1[(size_t)t * nl + p], bottom_get(rb[l], g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
             x1[l][p] = acc;
         }
         __syncthreads();
@@ -837,11 +904,13 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
         const T c1 = (T)st->c1[l - 1], c2 = (T)st->c2[l - 1];
         for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
             const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+            const T* __restrict__ k2 = a.k2[l];
             T acc = T(0);
+#pragma unroll
             for (int t = 0; t < kTaps; ++t) {
                 const int qz = z + t / 9 - 1, qy = y + (t / 3) % 3 - 1, qx = x + t % 3 - 1;
                 const T rv = in_grid(g, qz, qy, qx) ? interp_at<T>(xc, gc, qz, qy, qx) : T(0);
-                acc = fma(a.k2[l][(size_t)t * nl + p], rv, acc);
+                acc = fma(k2[(size_t)t * nl + p], rv, acc);
             }
             rb[l][p] = c1 * x1[l][p] + c2 * acc;
         }
@@ -876,7 +945,8 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         stage_image<true>(lab_s, lab, g, o);
@@ -927,7 +997,8 @@ __global__ __launch_bounds__(kBlock) void k_laplacian(const uint8_t* __restrict_
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
-    for (int tile = blockIdx.x; tile < tl.count(); tile += gridDim.x) {
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         stage_image<true>(lab_s, lab, g, o);
