@@ -30,6 +30,28 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
 
 
+def measured_traffic(kernel: str, workload_ok: bool):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by its reading on a
+    known-size kernel), or None when the kernel sources changed since the
+    counters were taken or the workload is not the profiled one."""
+    import glob
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not workload_ok or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    h = hashlib.sha256()
+    for src in sorted(glob.glob(os.path.join(ROOT, "paper_2310_00177_amd", "csrc", "*"))):
+        with open(src, "rb") as f:
+            h.update(f.read())
+    k = rec["kernels"].get(kernel)
+    if h.hexdigest() != rec["source_sha256"] or k is None:
+        return None
+    return k["fetch_bytes"] + k["write_bytes"]
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -42,7 +64,7 @@ def parse():
     ap.add_argument("--headline", default="mixed_bf16", choices=["mixed_bf16", "mixed_fp16", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp32", help="second precision to time, or 'none'")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="end with one 256 MiB device-to-device copy (a known-size kernel for HBM counters)")
+                    help="end with known-size fill and negate kernels (1 GiB each) for the HBM counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations in the CPU sample")
     ap.add_argument("--serving", action="store_true",
@@ -301,7 +323,8 @@ def main():
             "speedup_headline_vs_compare": head["solves_per_s"] / comp["solves_per_s"]},
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(dom, n == 128 and args.seed == 1 and args.headline == "mixed_bf16"),
             "bytes_per_launch": bytes_per_launch, "avg_launch_us": avg_s * 1e6,
             "iteration": {"alg_bytes": it_bytes, "us": per_iter_ms * 1e3,
                           "achieved_GBs": it_bytes / (per_iter_ms * 1e-3) / 1e9,
@@ -312,13 +335,19 @@ def main():
     }
     print(json.dumps(out))
     if args.calibrate_copy:
-        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        # A known-size kernel for the HBM counters: fill src (1 GiB), write
+        # another 1 GiB so src is evicted from the L2s and the 256 MB
+        # Infinity Cache, then negate src into dst (1 GiB read, 1 GiB written).
+        n = 256 << 20
+        src = torch.full((n,), 1.0, dtype=torch.float32, device="cuda")
+        flush = torch.zeros(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.neg(src, out=dst)
         torch.cuda.synchronize()
-        print("# calibration copy: 268435456 bytes read, 268435456 bytes written", file=sys.stderr)
-
+        del flush
+        print(f"# calibration: fill 2 x {4 * n} bytes written; neg {4 * n} bytes read, {4 * n} bytes written",
+              file=sys.stderr)
 
 if __name__ == "__main__":
     main()
