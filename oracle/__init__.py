@@ -10,6 +10,8 @@ Plain, slow, obviously correct NumPy in float64:
   network    -- the spatially-varying-kernel network (Alg. 2, CConv and Aff
                 formulas of Sec. "Architecture", 3D extension).
   npsdo      -- the NPSDO iteration (Alg. 1).
+  pcg        -- PCG and flexible PCG with the network (the solver variants
+                of the appendix comparing PCG variants).
   gradient   -- the training loss of Sec. "Training" and its adjoint.
 
 Every function states the passage it follows.  Readings of passages that are
@@ -19,4 +21,4 @@ Parity status: every function is pinned by the CPU test suite against
 closed forms, library routines or brute force, except the asymmetry measure
 S (a diagnostic: parity unpinned).
 """
-from . import laplacian, network, npsdo  # noqa: F401
+from . import laplacian, network, npsdo, pcg  # noqa: F401

@@ -102,5 +102,5 @@ def test_autograd_functions_match_oracle_batch_mean():
     loss = total / len(labs)
     loss.backward()
     loss_ref, grad_ref = og.batch_loss_and_grad(params, L, labs, bs)
-    assert float(loss) == pytest.approx(loss_ref, rel=1e-11)
+    assert loss.item() == pytest.approx(loss_ref, rel=1e-11)
     assert rel(p.grad.cpu().numpy(), grad_ref) <= 1e-9
