@@ -117,6 +117,7 @@ struct Layout {
     size_t rb[kMaxLevels + 1];
     size_t k1[kMaxLevels + 1], k2[kMaxLevels + 1];
     size_t dhat, dring[kRing], adring[kRing], x[2], r;
+    size_t wmode[kMaxLevels + 1][2];   // per-wave CConv modes: [level][down, up (level 1)]
     size_t total;
 };
 
@@ -141,6 +142,11 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
         const size_t nl = ncells(level_grid(d, l));
         L.k1[l] = put(s * kTaps * nl);
         if (l < levels) L.k2[l] = put(s * kTaps * nl);
+    }
+    for (int l = 1; l <= levels; ++l) {
+        const size_t waves = (size_t)tiles_of(level_grid(d, l)).count() * TZ;
+        L.wmode[l][0] = put(waves);
+        if (l == 1) L.wmode[l][1] = put(waves);
     }
     L.dhat = put(s * n);
     if (solve) {
@@ -379,6 +385,19 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
         }));
     }
     for (int l = 1; l <= L; ++l) {
+        const Grid g = level_grid(d, l);
+        const int grid = tile_grid(g);
+        int8_t* md = mptr<int8_t>(ws, lay.wmode[l][0]);
+        if (l == 1)
+            NPS_TRY(launch("setup_wave_modes", (double)ncells(g), s, [&] {
+                k_wave_modes<true><<<grid, kBlock, 0, s>>>(img(l), g, 1u, md, mptr<int8_t>(ws, lay.wmode[l][1]));
+            }));
+        else
+            NPS_TRY(launch("setup_wave_modes", (double)ncells(g), s, [&] {
+                k_wave_modes<false><<<grid, kBlock, 0, s>>>(img(l), g, full_count(l), md, nullptr);
+            }));
+    }
+    for (int l = 1; l <= L; ++l) {
         if (plan.km[l] != kStored) continue;
         const Grid g = level_grid(d, l);
         const int grid = elem_grid(ncells(g));
@@ -436,10 +455,12 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
             constexpr int KM = decltype(km)::value;
             if (l < L)
                 return launch("net_down", cells, s, [&] {
-                    k_down<T, KM, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, wm, kst, st);
+                    k_down<T, KM, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, wm, kst, st,
+                                                                 cptr<int8_t>(ws, lay.wmode[l][0]));
                 });
             return launch("net_coarsest", cells, s, [&] {
-                k_down<T, KM, false><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, nullptr, w, wm, kst, st);
+                k_down<T, KM, false><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, nullptr, w, wm, kst, st,
+                                                              cptr<int8_t>(ws, lay.wmode[l][0]));
             });
         }));
     }
@@ -476,7 +497,8 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
             constexpr int KM = decltype(km)::value;
             return launch("net_up", (double)ncells(g), s, [&] {
-                k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st, nullptr);
+                k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st, nullptr,
+                                                    cptr<int8_t>(ws, lay.wmode[l][0]));
             });
         }));
     }
@@ -501,7 +523,7 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
         constexpr int KM = decltype(km)::value;
         return launch("net_down_l1", (double)ncells(g), s, [&] {
             k_down_l1<T, X, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, b, xb0, xb1, dpend, r, x1, rnext, w, wm, kst, st,
-                                                              partials);
+                                                              partials, cptr<int8_t>(ws, lay.wmode[1][0]));
         });
     });
 }
@@ -523,7 +545,7 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
         constexpr int KM = decltype(km)::value;
         return launch("net_up_l1", (double)ncells(g), s, [&] {
             k_up_l1<T, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, kst, st, partials, ad[0], ad[1],
-                                                        ad[2], ad[3], nullptr);
+                                                        ad[2], ad[3], nullptr, cptr<int8_t>(ws, lay.wmode[1][1]));
         });
     });
 }
@@ -643,7 +665,17 @@ struct SolverT : Solver {
                                                                nullptr);
             }));
         NPS_TRY(launch("ortho_matvec", cells, s, [&] {
-            k_ortho<T><<<rgrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r, dk, adk, st, partials);
+            auto go = [&](auto no) {
+                k_ortho<T, decltype(no)::value><<<rgrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r,
+                                                                         dk, adk, st, partials);
+            };
+            switch (o.n_ortho) {
+                case 0: go(std::integral_constant<int, 0>{}); break;
+                case 1: go(std::integral_constant<int, 1>{}); break;
+                case 2: go(std::integral_constant<int, 2>{}); break;
+                case 3: go(std::integral_constant<int, 3>{}); break;
+                default: go(std::integral_constant<int, 4>{}); break;
+            }
         }));
         NPS_TRY(launch("control", 0, s, [&] {
             k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, slot, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
@@ -1037,11 +1069,13 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         const CConvW<T>* w = cconv_block<T>(net, block_down(l));
         if (l < L)
             NPS_TRY(launch("net_down", (double)ncells(g), s, [&] {
-                k_down<T, kStored, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, nullptr, kst, st);
+                k_down<T, kStored, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, nullptr, kst, st,
+                                                                  nullptr);
             }));
         else
             NPS_TRY(launch("net_coarsest", (double)ncells(g), s, [&] {
-                k_down<T, kStored, false><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, nullptr, w, nullptr, kst, st);
+                k_down<T, kStored, false><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, nullptr, w, nullptr, kst,
+                                                                   st, nullptr);
             }));
     }
     auto x_of = [&](int l) -> const T* { return l == L ? cptr<T>(ws, lay.x1[L]) : cptr<T>(ws, tl.xup[l]); };
@@ -1056,7 +1090,8 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         const T* kst = cptr<T>(ws, lay.k2[l]);
         const CConvW<T>* w = cconv_block<T>(net, block_up(net, l));
         NPS_TRY(launch("net_up", (double)ncells(g), s, [&] {
-            k_up<T, kStored><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, nullptr, kst, l - 1, st, x2o);
+            k_up<T, kStored><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, nullptr, kst, l - 1, st, x2o,
+                                                         nullptr);
         }));
     }
     {
@@ -1070,7 +1105,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         double* partials = mptr<double>(ws, lay.partials);
         NPS_TRY(launch("net_up_l1", (double)ncells(g), s, [&] {
             k_up_l1<T, kStored, true><<<grid, kBlock, 0, s>>>(labels, g, xc, x1, y, w, nullptr, kst, st, partials, nullptr,
-                                                            nullptr, nullptr, nullptr, x2o);
+                                                            nullptr, nullptr, nullptr, x2o, nullptr);
         }));
     }
     return NPS_OK;

@@ -27,6 +27,13 @@
 
 namespace nps {
 
+// Occupancy floor of a kernel (waves per SIMD): caps its registers at
+// 512 / n so that n waves of it fit per SIMD.
+#define NPS_WAVES_PER_EU(n) __attribute__((amdgpu_waves_per_eu(n)))
+
+// The three-piece bf16 weights of the FP32 MFMA path need more registers.
+constexpr int waves_floor(int km) { return km == kMfmaBf16x3 ? 3 : 4; }
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
@@ -35,7 +42,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // reductions
 // ---------------------------------------------------------------------------
-__device__ inline double wave_sum(double v) {
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
     return v;
@@ -43,7 +50,7 @@ __device__ inline double wave_sum(double v) {
 
 // Block sum of kRedWidth values; value w of block b goes to partials[w * kMaxRedBlocks + b].
 template <int NT>
-__device__ inline void block_partials(double (&v)[kRedWidth], double* partials) {
+__device__ __forceinline__ void block_partials(double (&v)[kRedWidth], double* partials) {
     __shared__ double sh[kRedWidth][NT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -77,7 +84,7 @@ struct TileSpan {
     int t0, t1, step;
 };
 
-__device__ inline TileSpan tile_span(int ntiles) {
+__device__ __forceinline__ TileSpan tile_span(int ntiles) {
     const int G = gridDim.x, b = blockIdx.x;
     if (G % kXcds != 0) return TileSpan{b, ntiles, G};
     const int chunk = (ntiles + kXcds - 1) / kXcds;
@@ -85,7 +92,7 @@ __device__ inline TileSpan tile_span(int ntiles) {
     return TileSpan{x * chunk + b / kXcds, min((x + 1) * chunk, ntiles), G / kXcds};
 }
 
-__device__ inline TileOrigin tile_origin(int tile, Tiles tl) {
+__device__ __forceinline__ TileOrigin tile_origin(int tile, Tiles tl) {
     TileOrigin o;
     o.x0 = (tile % tl.ntx) * TX;
     o.y0 = ((tile / tl.ntx) % tl.nty) * TY;
@@ -93,11 +100,11 @@ __device__ inline TileOrigin tile_origin(int tile, Tiles tl) {
     return o;
 }
 
-__device__ inline size_t cell_index(Grid g, int z, int y, int x) {
+__device__ __forceinline__ size_t cell_index(Grid g, int z, int y, int x) {
     return ((size_t)z * g.ny + y) * g.nx + x;
 }
 
-__device__ inline bool in_grid(Grid g, int z, int y, int x) {
+__device__ __forceinline__ bool in_grid(Grid g, int z, int y, int x) {
     return x >= 0 && y >= 0 && z >= 0 && x < g.nx && y < g.ny && z < g.nz;
 }
 
@@ -106,26 +113,91 @@ __host__ __device__ constexpr int halo_off(int o) {
     return (o / 9 - 1) * HY * HX + ((o / 3) % 3 - 1) * HX + (o % 3 - 1);
 }
 
-__device__ inline int halo_base(int lx, int ly, int lz) { return ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1); }
+__device__ __forceinline__ int halo_base(int lx, int ly, int lz) { return ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1); }
 
-// Stage the image of a level over the haloed tile.  Level 1: labels (out of
-// grid -> solid).  Coarser levels: packed counts n_fluid | n_air << 16 (out
-// of grid -> 0, i.e. solid).
+// Stage NH elements of a tile into LDS in two phases: get(i) only issues
+// the global loads of element i (clamped, always valid addresses, no use of
+// the loaded values, so the phase is straight-line code), then put(i, v)
+// forms and stores the elements.  Every load of the thread is in flight
+// before the first put, so the tile waits for one memory latency rather than
+// one per element.  The last, partial round reloads element NH - 1 where it
+// runs past the end and stores it past the end: the destination arrays hold
+// whole rounds (pad_block), and nothing reads the padding.
+template <int NH, class V, class Get, class Put>
+__device__ __forceinline__ void stage_batched(Get get, Put put) {
+    constexpr int K = (NH + kBlock - 1) / kBlock;
+    V v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = get(min((int)threadIdx.x + k * kBlock, NH - 1));
+#pragma unroll
+    for (int k = 0; k < K; ++k) put(threadIdx.x + k * kBlock, v[k]);
+}
+
+// Two stagings of one tile with all their loads in flight together.
+template <int N1, class V1, int N2, class V2, class Get1, class Put1, class Get2, class Put2>
+__device__ __forceinline__ void stage_batched2(Get1 get1, Put1 put1, Get2 get2, Put2 put2) {
+    constexpr int K1 = (N1 + kBlock - 1) / kBlock, K2 = (N2 + kBlock - 1) / kBlock;
+    V1 v1[K1];
+    V2 v2[K2];
+#pragma unroll
+    for (int k = 0; k < K1; ++k) v1[k] = get1(min((int)threadIdx.x + k * kBlock, N1 - 1));
+#pragma unroll
+    for (int k = 0; k < K2; ++k) v2[k] = get2(min((int)threadIdx.x + k * kBlock, N2 - 1));
+#pragma unroll
+    for (int k = 0; k < K1; ++k) put1(threadIdx.x + k * kBlock, v1[k]);
+#pragma unroll
+    for (int k = 0; k < K2; ++k) put2(threadIdx.x + k * kBlock, v2[k]);
+}
+
+// Grid coordinates of element i of the one-cell haloed tile.
+__device__ __forceinline__ void halo_coords(int i, TileOrigin o, int& x, int& y, int& z) {
+    x = o.x0 + i % HX - 1;
+    y = o.y0 + (i / HX) % HY - 1;
+    z = o.z0 + i / (HX * HY) - 1;
+}
+
+// Global address (cell index, 0 when outside) of element i of the one-cell
+// haloed tile, and whether it lies inside the grid.
+struct HaloCell {
+    size_t q;
+    bool in;
+};
+
+__device__ __forceinline__ HaloCell halo_cell(Grid g, TileOrigin o, int i) {
+    int x, y, z;
+    halo_coords(i, o, x, y, z);
+    const bool in = in_grid(g, z, y, x);
+    return HaloCell{in ? cell_index(g, z, y, x) : 0, in};
+}
+
+// The image of a level over the haloed tile.  Level 1: labels (out of grid
+// -> solid).  Coarser levels: packed counts n_fluid | n_air << 16 (out of
+// grid -> 0, i.e. solid).
+struct ImgLoad {
+    uint32_t v;
+    bool in;
+};
+
 template <bool L1>
-__device__ inline void stage_image(uint32_t* img_s, const void* img, Grid g, TileOrigin o) {
-    for (int i = threadIdx.x; i < kHalo; i += kBlock) {
-        const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        const int x = o.x0 + hx - 1, y = o.y0 + hy - 1, z = o.z0 + hz - 1;
-        const bool in = in_grid(g, z, y, x);
-        uint32_t v;
-        if (L1) v = in ? (uint32_t)static_cast<const uint8_t*>(img)[cell_index(g, z, y, x)] : (uint32_t)kSolid;
-        else v = in ? static_cast<const uint32_t*>(img)[cell_index(g, z, y, x)] : 0u;
-        img_s[i] = v;
-    }
+__device__ __forceinline__ ImgLoad image_load(const void* img, Grid g, TileOrigin o, int i) {
+    const HaloCell c = halo_cell(g, o, i);
+    if constexpr (L1) return ImgLoad{(uint32_t)static_cast<const uint8_t*>(img)[c.q], c.in};
+    else return ImgLoad{static_cast<const uint32_t*>(img)[c.q], c.in};
 }
 
 template <bool L1>
-__device__ inline void counts_of(uint32_t v, uint32_t& n0, uint32_t& n1) {
+__device__ __forceinline__ uint32_t image_value(ImgLoad a) {
+    return a.in ? a.v : (L1 ? (uint32_t)kSolid : 0u);
+}
+
+template <bool L1>
+__device__ __forceinline__ void stage_image(uint32_t* img_s, const void* img, Grid g, TileOrigin o) {
+    stage_batched<kHalo, ImgLoad>([&](int i) { return image_load<L1>(img, g, o, i); },
+                                  [&](int i, ImgLoad v) { img_s[i] = image_value<L1>(v); });
+}
+
+template <bool L1>
+__device__ __forceinline__ void counts_of(uint32_t v, uint32_t& n0, uint32_t& n1) {
     if (L1) {
         n0 = v == kFluid;
         n1 = v == kAir;
@@ -138,7 +210,7 @@ __device__ inline void counts_of(uint32_t v, uint32_t& n0, uint32_t& n1) {
 // Window class of the cell at `base`: pure label c (0..2) when all 27 window
 // cells are pure cells of label c, else -1.  any_fluid: a window cell holds fluid.
 template <bool L1>
-__device__ inline int window_class(const uint32_t* img_s, int base, uint32_t full, bool& any_fluid) {
+__device__ __forceinline__ int window_class(const uint32_t* img_s, int base, uint32_t full, bool& any_fluid) {
     int cls = -2;
     bool mixed = false;
     any_fluid = false;
@@ -164,7 +236,7 @@ __device__ inline int window_class(const uint32_t* img_s, int base, uint32_t ful
 // zero, 0..2 every window of the wave is pure label c (constant kernel),
 // -1 general.
 template <bool L1>
-__device__ inline int choose_mode(bool active, const uint32_t* img_s, int base, uint32_t full,
+__device__ __forceinline__ int choose_mode(bool active, const uint32_t* img_s, int base, uint32_t full,
                                   bool zero_if_no_fluid, bool out_only_on_fluid) {
     bool any_fluid = false;
     int cls = -1;
@@ -180,12 +252,23 @@ __device__ inline int choose_mode(bool active, const uint32_t* img_s, int base, 
     return -1;
 }
 
+// The mode of the calling wave for tile `tile`: from the table formed at
+// setup (k_wave_modes; the labels do not change during a solve) when given,
+// else computed here.  Wave-uniform.
+template <bool L1>
+__device__ __forceinline__ int wave_mode(const int8_t* __restrict__ tab, int tile, int lz, bool active,
+                                         const uint32_t* img_s, int base, uint32_t full, bool zero_if_no_fluid,
+                                         bool out_only_on_fluid) {
+    if (tab) return tab[__builtin_amdgcn_readfirstlane(tile * TZ + lz)];
+    return choose_mode<L1>(active, img_s, base, full, zero_if_no_fluid, out_only_on_fluid);
+}
+
 // ---------------------------------------------------------------------------
 // CConv evaluation of one output cell, per kernel-generation mode
 // ---------------------------------------------------------------------------
 // Vector ALU: K from the count form, then the 27-tap apply.
 template <class T, bool L1>
-__device__ inline T cconv_vector(const uint32_t* img_s, const T* r_s, int base, const CConvW<T>* __restrict__ w) {
+__device__ __forceinline__ T cconv_vector(const uint32_t* img_s, const T* r_s, int base, const CConvW<T>* __restrict__ w) {
     T K[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) K[t] = w->C[t];
@@ -204,7 +287,7 @@ __device__ inline T cconv_vector(const uint32_t* img_s, const T* r_s, int base, 
 }
 
 template <class T>
-__device__ inline T cconv_pure(const T* r_s, int base, const CConvW<T>* __restrict__ w, int c) {
+__device__ __forceinline__ T cconv_pure(const T* r_s, int base, const CConvW<T>* __restrict__ w, int c) {
     T acc = T(0);
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) acc = fma(w->Kpure[c][t], r_s[base + halo_off(t)], acc);
@@ -213,16 +296,80 @@ __device__ inline T cconv_pure(const T* r_s, int base, const CConvW<T>* __restri
 
 // Stored kernels: K[t][cell] formed at setup.
 template <class T>
-__device__ inline T cconv_stored(const T* r_s, int base, const T* __restrict__ kst, size_t n, size_t idx) {
+__device__ __forceinline__ T cconv_stored(const T* r_s, int base, const T* __restrict__ kst, size_t n, size_t idx) {
     T acc = T(0);
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) acc = fma(kst[(size_t)t * n + idx], r_s[base + halo_off(t)], acc);
     return acc;
 }
 
-__device__ inline int halo_off_rt(int o) {   // runtime version of halo_off
+__device__ __forceinline__ int halo_off_rt(int o) {   // runtime version of halo_off
     const int oz = o / 9, oy = (o / 3) - 3 * oz, ox = o - 3 * (o / 3);
     return (oz - 1) * HY * HX + (oy - 1) * HX + (ox - 1);
+}
+
+__host__ __device__ constexpr bool is_mfma(int km) { return km == kMfmaBf16x3 || km == kMfmaBf16 || km == kMfmaF16; }
+
+// The two MFMA features of one window cell as one word, in the B-operand
+// element order: the fluid count in the low half, the air count in the high
+// half, each as bf16 (small integers: the top half of the fp32 pattern,
+// exactly) or fp16.  Staged once per haloed tile cell.
+template <int KM, bool L1>
+__device__ __forceinline__ uint32_t feat_word(uint32_t v) {
+    uint32_t c0, c1;
+    counts_of<L1>(v, c0, c1);
+    if constexpr (KM == kMfmaF16)
+        return (uint32_t)__builtin_bit_cast(unsigned short, (_Float16)(float)c0) |
+               ((uint32_t)__builtin_bit_cast(unsigned short, (_Float16)(float)c1) << 16);
+    else
+        return (__float_as_uint((float)c0) >> 16) | (__float_as_uint((float)c1) & 0xffff0000u);
+}
+
+// Feature pair 54/55 of the second feature step: the constant 1 (carrying
+// C) and a zero.
+template <int KM>
+__device__ __forceinline__ uint32_t feat_one() {
+    return KM == kMfmaF16 ? 0x3c00u : 0x3f80u;
+}
+
+// What a wave keeps for all its MFMA CConvs: the weight fragments (A
+// operand), the haloed-tile index of its lane's cell in row 0, and the
+// offsets of the lane's window positions 16 s + 4 g + j (s = feature step or
+// tap block, g = lane / 16, j < 4; positions past 26 clamped, their A rows
+// and columns are zero).  The same offsets address the features (window
+// offset o) and the taps (tap t) because both run over the 27 positions in
+// the same order.
+template <int KM>
+struct MfmaCtx {
+    static constexpr int P = KM == kMfmaBf16x3 ? kPieces : 1;
+    u16x8 a[P][2][2];
+    int base0;
+    int off[2][4];
+    bool one;   // lane group 2: word 3 of step 1 is feature pair 54/55
+};
+
+template <int KM>
+__device__ __forceinline__ MfmaCtx<KM> mfma_ctx(const MfmaW* __restrict__ wm, int lz) {
+    MfmaCtx<KM> c;
+    if constexpr (is_mfma(KM)) {
+        const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+#pragma unroll
+        for (int p = 0; p < MfmaCtx<KM>::P; ++p)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int ks = 0; ks < 2; ++ks) {
+                    const uint16_t* src = KM == kMfmaF16 ? &wm->f16[mb][ks][lane][0] : &wm->bf16[p][mb][ks][lane][0];
+                    c.a[p][mb][ks] = *reinterpret_cast<const u16x8*>(src);
+                }
+        c.base0 = halo_base(n, 0, lz);
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) c.off[s2][j] = halo_off_rt(min(16 * s2 + 4 * g + j, kTaps - 1));
+        c.one = g == 2;
+    }
+    return c;
 }
 
 // MFMA: one wave evaluates the CConv of its 64 cells (one z-plane of the
@@ -232,41 +379,25 @@ __device__ inline int halo_off_rt(int o) {   // runtime version of halo_off
 // times the bf16 pieces); each lane then applies its 8 taps of one cell and
 // the four lane groups are summed with two butterflies.  Returns the output
 // of the lane's own cell.  All 64 lanes must call it.
-template <int KM, bool L1>
-__device__ inline float cconv_mfma(const uint32_t* img_s, const float* r_s, int lz, const MfmaW* __restrict__ wm) {
-    constexpr int P = KM == kMfmaBf16x3 ? kPieces : 1;
-    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
-    u16x8 A[P][2][2];
-#pragma unroll
-    for (int p = 0; p < P; ++p)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int ks = 0; ks < 2; ++ks) {
-                const uint16_t* src = KM == kMfmaF16 ? &wm->f16[mb][ks][lane][0] : &wm->bf16[p][mb][ks][lane][0];
-                A[p][mb][ks] = *reinterpret_cast<const u16x8*>(src);
-            }
+template <int KM>
+__device__ __forceinline__ float cconv_mfma(const uint32_t* feat_s, const float* r_s, const MfmaCtx<KM>& c) {
+    constexpr int P = MfmaCtx<KM>::P;
+    const int g = (threadIdx.x & 63) >> 4;
     float mine = 0.0f;
-#pragma unroll
+#pragma unroll 1
     for (int q = 0; q < 4; ++q) {
-        const int base = halo_base(n, q, lz);
+        const int bq = c.base0 + q * HX;
+        uint32_t wv[2][4];
+#pragma unroll
+        for (int ks = 0; ks < 2; ++ks)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) wv[ks][j] = feat_s[bq + c.off[ks][j]];
+        wv[1][3] = c.one ? feat_one<KM>() : wv[1][3];
         u16x8 B[2];
 #pragma unroll
         for (int ks = 0; ks < 2; ++ks) {
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int o = 16 * ks + 4 * g + j;          // window offset of features 2j, 2j+1
-                uint32_t c0 = 0, c1 = 0;
-                if (o < kTaps) counts_of<L1>(img_s[base + halo_off_rt(o)], c0, c1);
-                else if (o == kTaps) c0 = 1;                 // feature 54: the constant 1
-                if (KM == kMfmaF16) {
-                    B[ks][2 * j] = __builtin_bit_cast(unsigned short, (_Float16)(float)c0);
-                    B[ks][2 * j + 1] = __builtin_bit_cast(unsigned short, (_Float16)(float)c1);
-                } else {   // small integers: the bf16 is the top half of the fp32 pattern, exactly
-                    B[ks][2 * j] = (unsigned short)(__float_as_uint((float)c0) >> 16);
-                    B[ks][2 * j + 1] = (unsigned short)(__float_as_uint((float)c1) >> 16);
-                }
-            }
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            B[ks] = __builtin_bit_cast(u16x8, (u32x4){wv[ks][0], wv[ks][1], wv[ks][2], wv[ks][3]});
         }
         f32x4 acc[2];
 #pragma unroll
@@ -277,10 +408,10 @@ __device__ inline float cconv_mfma(const uint32_t* img_s, const float* r_s, int 
 #pragma unroll
                 for (int ks = 0; ks < 2; ++ks) {
                     if (KM == kMfmaF16)
-                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, A[p][mb][ks]),
+                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, c.a[p][mb][ks]),
                                                                          __builtin_bit_cast(f16x8, B[ks]), acc[mb], 0, 0, 0);
                     else
-                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A[p][mb][ks]),
+                        acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, c.a[p][mb][ks]),
                                                                           __builtin_bit_cast(bf16x8, B[ks]), acc[mb], 0, 0, 0);
                 }
         }
@@ -288,10 +419,7 @@ __device__ inline float cconv_mfma(const uint32_t* img_s, const float* r_s, int 
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int t = min(16 * mb + 4 * g + i, kTaps - 1);   // rows >= 27 hold zero kernels
-                part = fmaf(acc[mb][i], r_s[base + halo_off_rt(t)], part);
-            }
+            for (int i = 0; i < 4; ++i) part = fmaf(acc[mb][i], r_s[bq + c.off[mb][i]], part);
         part += __shfl_xor(part, 16, 64);
         part += __shfl_xor(part, 32, 64);
         if (q == g) mine = part;
@@ -301,9 +429,9 @@ __device__ inline float cconv_mfma(const uint32_t* img_s, const float* r_s, int 
 
 // One CConv output of the thread's cell (lx, ly, lz) for a wave-uniform mode.
 template <class T, int KM, bool L1>
-__device__ inline T cconv_any(int mode, bool active, const uint32_t* img_s, const T* r_s, int base, int lz,
-                              const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
-                              const T* __restrict__ kst, size_t n, size_t idx) {
+__device__ __forceinline__ T cconv_any(int mode, bool active, const uint32_t* img_s, const uint32_t* feat_s,
+                                       const T* r_s, int base, const CConvW<T>* __restrict__ w,
+                                       const MfmaCtx<KM>& mc, const T* __restrict__ kst, size_t n, size_t idx) {
     if (mode == -3) return T(0);
     if (mode >= 0) return active ? cconv_pure<T>(r_s, base, w, mode) : T(0);
     if constexpr (KM == kStored) {
@@ -312,7 +440,7 @@ __device__ inline T cconv_any(int mode, bool active, const uint32_t* img_s, cons
         return active ? cconv_vector<T, L1>(img_s, r_s, base, w) : T(0);
     } else {
         static_assert(sizeof(T) == 4, "MFMA paths are float");
-        return cconv_mfma<KM, L1>(img_s, reinterpret_cast<const float*>(r_s), lz, wm);
+        return cconv_mfma<KM>(feat_s, reinterpret_cast<const float*>(r_s), mc);
     }
 }
 
@@ -322,7 +450,7 @@ __device__ inline T cconv_any(int mode, bool active, const uint32_t* img_s, cons
 // "Spatial Discretization").
 // sx: stride of y, sz: stride of z; Acc: accumulation type.
 template <class Acc, class V, class L>
-__device__ inline Acc apply_A(const L* lab_s, const V* v_s, int base, int sx, int sz) {
+__device__ __forceinline__ Acc apply_A(const L* lab_s, const V* v_s, int base, int sx, int sz) {
     if (lab_s[base] != kFluid) return Acc(0);
     const int nb[6] = {-sz, sz, -sx, sx, -1, 1};
     int cnt = 0;
@@ -454,6 +582,33 @@ __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ 
 // Sums nparts per-block partials (structure of arrays, block order: a fixed
 // summation order) and updates the state for one stage of the iteration.
 // The stopping decision is mirrored to host memory (hf) for the host loop.
+// Per-wave CConv modes of one level (see choose_mode), one byte per (tile,
+// z-plane of the tile).  Level 1: m_down for the down kernel (zero where no
+// window of the wave holds fluid), m_up for the up kernel (zero where the
+// wave has no fluid cell).  Coarser levels: pure-window classes in m_down.
+template <bool L1>
+__global__ __launch_bounds__(kBlock) void k_wave_modes(const void* __restrict__ img, Grid g, uint32_t full,
+                                                       int8_t* __restrict__ m_down, int8_t* __restrict__ m_up) {
+    __shared__ uint32_t img_s[kHaloP];
+    const Tiles tl = tiles_of(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int tile = sp.t0;
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        stage_image<L1>(img_s, img, g, o);
+        __syncthreads();
+        const bool active = in_grid(g, o.z0 + lz, o.y0 + ly, o.x0 + lx);
+        const int md = choose_mode<L1>(active, img_s, base, full, L1, false);
+        const int mu = L1 ? choose_mode<L1>(active, img_s, base, full, false, true) : md;
+        if ((threadIdx.x & 63) == 0) {
+            m_down[tile * TZ + lz] = (int8_t)md;
+            if (L1) m_up[tile * TZ + lz] = (int8_t)mu;
+        }
+    }
+}
+
 template <int STAGE>
 __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* __restrict__ partials, int nparts,
                                                        int i0, int i1, int i2, int i3, double d0, double d1,
@@ -541,7 +696,7 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
 // network kernels (Alg. 2)
 // ---------------------------------------------------------------------------
 template <class T>
-__device__ inline void pool_tile_to(const T* out_s, TileOrigin o, Grid g, T* rnext) {
+__device__ __forceinline__ void pool_tile_to(const T* out_s, TileOrigin o, Grid g, T* rnext) {
     if (threadIdx.x < kBlock / 8) {
         const int cx = threadIdx.x % (TX / 2), cy = (threadIdx.x / (TX / 2)) % (TY / 2),
                   cz = threadIdx.x / ((TX / 2) * (TY / 2));
@@ -567,17 +722,19 @@ __device__ inline void pool_tile_to(const T* out_s, TileOrigin o, Grid g, T* rne
 // value another block has already updated.  HOOK (nps_apply_precond): r is
 // the input, masked to fluid.  Then x1 = CConv_1^1(r) and r^2 = Pool(x1).
 template <class T, class X, int KM, bool HOOK>
-__global__ __launch_bounds__(kBlock) void k_down_l1(
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_down_l1(
     const uint8_t* __restrict__ lab, Grid g, const double* __restrict__ b, X* xb0, X* xb1,
     const T* __restrict__ dpend, T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
     const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
-    const State* st, double* partials) {
+    const State* st, double* partials, const int8_t* __restrict__ wmode) {
     if (!HOOK && st->done) return;
-    __shared__ uint32_t img_s[kHalo];
-    __shared__ T r_s[kHalo];
+    __shared__ uint32_t img_s[kHaloP];
+    __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
+    __shared__ T r_s[kHaloP];
     __shared__ T out_s[kBlock];
-    __shared__ uint8_t lab2_s[HOOK ? 1 : kHalo2];
-    __shared__ X x2_s[HOOK ? 1 : kHalo2];
+    __shared__ uint8_t lab2_s[HOOK ? 1 : kHalo2P];
+    __shared__ X x2_s[HOOK ? 1 : kHalo2P];
+    __shared__ double b_s[HOOK ? 1 : kHaloP];
     const bool pend = !HOOK && st->pending;
     const X alpha = HOOK ? X(0) : (X)st->alpha;
     const int cur = HOOK ? 0 : st->xcur;
@@ -587,46 +744,72 @@ __global__ __launch_bounds__(kBlock) void k_down_l1(
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
+    const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
     for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image<true>(img_s, lab, g, o);
         if (HOOK) {
-            for (int i = threadIdx.x; i < kHalo; i += kBlock) {
-                const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-                const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
-                T val = T(0);
-                if (in_grid(g, zz, yy, xx) && lab[cell_index(g, zz, yy, xx)] == kFluid) val = r[cell_index(g, zz, yy, xx)];
-                r_s[i] = val;
-            }
+            struct LR {
+                T r;
+                uint8_t l;
+                bool in;
+            };
+            stage_batched<kHalo, LR>(
+                [&](int i) {
+                    const HaloCell c = halo_cell(g, o, i);
+                    return LR{r[c.q], lab[c.q], c.in};
+                },
+                [&](int i, LR v) {
+                    r_s[i] = v.in && v.l == kFluid ? v.r : T(0);
+                    const uint32_t l = v.in ? v.l : (uint32_t)kSolid;
+                    img_s[i] = l;
+                    if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(l);
+                });
         } else {
-            // x (+ alpha d) and labels over the two-cell halo
-            for (int i = threadIdx.x; i < kHalo2; i += kBlock) {
-                const int hx = i % H2X, hy = (i / H2X) % H2Y, hz = i / (H2X * H2Y);
-                const int xx = o.x0 + hx - 2, yy = o.y0 + hy - 2, zz = o.z0 + hz - 2;
-                X xv = X(0);
-                uint8_t l = kSolid;
-                if (in_grid(g, zz, yy, xx)) {
-                    const size_t q = cell_index(g, zz, yy, xx);
-                    l = lab[q];
-                    xv = x[q];
-                    if (pend) xv += alpha * (X)dpend[q];
-                }
-                lab2_s[i] = l;
-                x2_s[i] = xv;
-            }
+            // x (+ alpha d) and labels over the two-cell halo, and b over the
+            // one-cell halo, all loads in flight together
+            struct XDL {
+                X x;
+                T d;
+                uint8_t l;
+                bool in;
+            };
+            struct BL {
+                double b;
+                bool in;
+            };
+            stage_batched2<kHalo2, XDL, kHalo, BL>(
+                [&](int i) {
+                    const int xx = o.x0 + i % H2X - 2, yy = o.y0 + (i / H2X) % H2Y - 2, zz = o.z0 + i / (H2X * H2Y) - 2;
+                    const bool in = in_grid(g, zz, yy, xx);
+                    const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
+                    return XDL{x[q], dpend[q], lab[q], in};
+                },
+                [&](int i, XDL v) {
+                    X xv = v.x;
+                    if (pend) xv += alpha * (X)v.d;
+                    lab2_s[i] = v.in ? v.l : (uint8_t)kSolid;
+                    x2_s[i] = v.in ? xv : X(0);
+                },
+                [&](int i) {
+                    const HaloCell c = halo_cell(g, o, i);
+                    return BL{b[c.q], c.in};
+                },
+                [&](int i, BL v) { b_s[i] = v.in ? v.b : 0.0; });
             __syncthreads();
-            // r = b - A x over the tile and its one-cell halo (zero off fluid / off grid)
+            // r = b - A x over the tile and its one-cell halo (zero off fluid /
+            // off grid); the labels of the same cells become the image.
             for (int i = threadIdx.x; i < kHalo; i += kBlock) {
                 const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-                const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
                 const int b2 = ((hz + 1) * H2Y + (hy + 1)) * H2X + (hx + 1);
+                const uint8_t l = lab2_s[b2];
                 double rv = 0.0;
-                if (in_grid(g, zz, yy, xx) && lab2_s[b2] == kFluid)
-                    rv = b[cell_index(g, zz, yy, xx)] - apply_A<double, X, uint8_t>(lab2_s, x2_s, b2, H2X, H2X * H2Y);
+                if (l == kFluid) rv = b_s[i] - apply_A<double, X, uint8_t>(lab2_s, x2_s, b2, H2X, H2X * H2Y);
                 r_s[i] = (T)rv;
+                img_s[i] = l;
+                if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(l);
             }
         }
         __syncthreads();
@@ -640,8 +823,8 @@ __global__ __launch_bounds__(kBlock) void k_down_l1(
             r[idx] = rv;
             v[0] += (double)rv * (double)rv;
         }
-        const int mode = choose_mode<true>(active, img_s, base, 1u, true, false);
-        const T out = cconv_any<T, KM, true>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        const int mode = wave_mode<true>(wmode, tile, lz, active, img_s, base, 1u, true, false);
+        const T out = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) x1[idx] = out;
         out_s[threadIdx.x] = active ? out : T(0);
         __syncthreads();
@@ -652,34 +835,47 @@ __global__ __launch_bounds__(kBlock) void k_down_l1(
 
 // x1 = CConv_1(r, I) on one level l >= 2, and (POOL) r_next = Pool(x1).
 template <class T, int KM, bool POOL>
-__global__ __launch_bounds__(kBlock) void k_down(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_down(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
                                                  const T* __restrict__ rin, T* __restrict__ x1, T* __restrict__ rnext,
                                                  const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
-                                                 const T* __restrict__ kst, const State* st) {
+                                                 const T* __restrict__ kst, const State* st,
+                                                 const int8_t* __restrict__ wmode) {
     if (st->done) return;
-    __shared__ uint32_t img_s[kHalo];
-    __shared__ T r_s[kHalo];
+    __shared__ uint32_t img_s[kHaloP];
+    __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
+    __shared__ T r_s[kHaloP];
     __shared__ T out_s[kBlock];
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
+    const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image<false>(img_s, cnt, g, o);
-        for (int i = threadIdx.x; i < kHalo; i += kBlock) {
-            const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-            const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
-            r_s[i] = in_grid(g, zz, yy, xx) ? rin[cell_index(g, zz, yy, xx)] : T(0);
-        }
+        struct CR {
+            uint32_t c;
+            T r;
+            bool in;
+        };
+        stage_batched<kHalo, CR>(
+            [&](int i) {
+                const HaloCell c = halo_cell(g, o, i);
+                return CR{cnt[c.q], rin[c.q], c.in};
+            },
+            [&](int i, CR v) {
+                const uint32_t c = v.in ? v.c : 0u;
+                img_s[i] = c;
+                if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, false>(c);
+                r_s[i] = v.in ? v.r : T(0);
+            });
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        const int mode = KM == kStored ? -1 : choose_mode<false>(active, img_s, base, full, false, false);
-        const T out = cconv_any<T, KM, false>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, tile, lz, active, img_s, base, full, false, false);
+        const T out = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) x1[idx] = out;
         if (POOL) {
             out_s[threadIdx.x] = active ? out : T(0);
@@ -691,13 +887,13 @@ __global__ __launch_bounds__(kBlock) void k_down(const uint32_t* __restrict__ cn
 
 // Linear 2x upsampling weights along one axis (cell-centred, edges clamped):
 // fine f -> coarse j = f/2 (weight 3/4) and its neighbour on f's side (1/4).
-__device__ inline void up_axis(int f, int nc, int& j, int& jn) {
+__device__ __forceinline__ void up_axis(int f, int nc, int& j, int& jn) {
     j = f >> 1;
     jn = (f & 1) ? min(j + 1, nc - 1) : max(j - 1, 0);
 }
 
 template <class T>
-__device__ inline T interp_at(const T* __restrict__ xc, Grid gc, int z, int y, int x) {
+__device__ __forceinline__ T interp_at(const T* __restrict__ xc, Grid gc, int z, int y, int x) {
     int jx, jxn, jy, jyn, jz, jzn;
     up_axis(x, gc.nx, jx, jxn);
     up_axis(y, gc.ny, jy, jyn);
@@ -718,17 +914,27 @@ __device__ inline T interp_at(const T* __restrict__ xc, Grid gc, int z, int y, i
 // LDS without further clamping.
 constexpr int CXS = TX / 2 + 4, CYS = TY / 2 + 4, CZS = TZ / 2 + 4;
 constexpr int kCoarseTile = CXS * CYS * CZS;
+constexpr int kCoarseTileP = pad_block(kCoarseTile);
 
-template <class T>
-__device__ inline void stage_interp(T* r_s, T* c_s, const T* __restrict__ xc, Grid g, TileOrigin o) {
+template <bool L1, int KM, class T>
+__device__ __forceinline__ void stage_image_interp(uint32_t* img_s, uint32_t* feat_s, const void* img, T* r_s, T* c_s,
+                                                   const T* __restrict__ xc, Grid g, TileOrigin o) {
     const Grid gc = coarser(g);
     const int bx = o.x0 / 2 - 2, by = o.y0 / 2 - 2, bz = o.z0 / 2 - 2;
-    for (int i = threadIdx.x; i < kCoarseTile; i += kBlock) {
-        const int cx = i % CXS, cy = (i / CXS) % CYS, cz = i / (CXS * CYS);
-        const int jx = min(max(bx + cx, 0), gc.nx - 1), jy = min(max(by + cy, 0), gc.ny - 1),
-                  jz = min(max(bz + cz, 0), gc.nz - 1);
-        c_s[i] = xc[cell_index(gc, jz, jy, jx)];
-    }
+    stage_batched2<kHalo, ImgLoad, kCoarseTile, T>(
+        [&](int i) { return image_load<L1>(img, g, o, i); },
+        [&](int i, ImgLoad v) {
+            const uint32_t u = image_value<L1>(v);
+            img_s[i] = u;
+            if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, L1>(u);
+        },
+        [&](int i) {
+            const int cx = i % CXS, cy = (i / CXS) % CYS, cz = i / (CXS * CYS);
+            const int jx = min(max(bx + cx, 0), gc.nx - 1), jy = min(max(by + cy, 0), gc.ny - 1),
+                      jz = min(max(bz + cz, 0), gc.nz - 1);
+            return xc[cell_index(gc, jz, jy, jx)];
+        },
+        [&](int i, T v) { c_s[i] = v; });
     __syncthreads();
     const T a = T(0.75), b = T(0.25);
     for (int i = threadIdx.x; i < kHalo; i += kBlock) {
@@ -751,33 +957,36 @@ __device__ inline void stage_interp(T* r_s, T* c_s, const T* __restrict__ xc, Gr
 
 // x = c1 x1 + c2 CConv_2(Interp(xc), I) on one level l >= 2.
 template <class T, int KM>
-__global__ __launch_bounds__(kBlock) void k_up(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
                                                const T* __restrict__ xc, const T* __restrict__ x1,
                                                T* __restrict__ xout, const CConvW<T>* __restrict__ w,
                                                const MfmaW* __restrict__ wm, const T* __restrict__ kst, int lvl,
-                                               const State* st, T* __restrict__ x2out) {
+                                               const State* st, T* __restrict__ x2out,
+                                               const int8_t* __restrict__ wmode) {
     if (st->done) return;
-    __shared__ uint32_t img_s[kHalo];
-    __shared__ T r_s[kHalo];
-    __shared__ T c_s[kCoarseTile];
+    __shared__ uint32_t img_s[kHaloP];
+    __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
+    __shared__ T r_s[kHaloP];
+    __shared__ T c_s[kCoarseTileP];
     const T c1 = (T)st->c1[lvl], c2 = (T)st->c2[lvl];
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
+    const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image<false>(img_s, cnt, g, o);
-        stage_interp<T>(r_s, c_s, xc, g, o);
+        stage_image_interp<false, KM, T>(img_s, feat_s, cnt, r_s, c_s, xc, g, o);
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        const int mode = KM == kStored ? -1 : choose_mode<false>(active, img_s, base, full, false, false);
-        const T x2 = cconv_any<T, KM, false>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
-        if (active) xout[idx] = c1 * x1[idx] + c2 * x2;
+        const T x1v = x1[idx];
+        const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, tile, lz, active, img_s, base, full, false, false);
+        const T x2 = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
+        if (active) xout[idx] = c1 * x1v + c2 * x2;
         if (active && x2out) x2out[idx] = x2;
     }
 }
@@ -786,15 +995,17 @@ __global__ __launch_bounds__(kBlock) void k_up(const uint32_t* __restrict__ cnt,
 // fluid cells (0 elsewhere), and the partial dots dhat . A d_i with the
 // stored A d_i of the previous directions.
 template <class T, int KM, bool HOOK>
-__global__ __launch_bounds__(kBlock) void k_up_l1(
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up_l1(
     const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ xc, const T* __restrict__ x1,
     T* __restrict__ dhat, const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
     const T* __restrict__ kst, const State* st, double* partials, const T* __restrict__ ad0,
-    const T* __restrict__ ad1, const T* __restrict__ ad2, const T* __restrict__ ad3, T* __restrict__ x2out) {
+    const T* __restrict__ ad1, const T* __restrict__ ad2, const T* __restrict__ ad3, T* __restrict__ x2out,
+    const int8_t* __restrict__ wmode) {
     if (!HOOK && st->done) return;
-    __shared__ uint32_t img_s[kHalo];
-    __shared__ T r_s[kHalo];
-    __shared__ T c_s[kCoarseTile];
+    __shared__ uint32_t img_s[kHaloP];
+    __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
+    __shared__ T r_s[kHaloP];
+    __shared__ T c_s[kCoarseTileP];
     const T c1 = (T)st->c1[0], c2 = (T)st->c2[0];
     const T scale = HOOK ? T(1) : (T)st->scale;
     const int nprev = HOOK ? 0 : st->nprev;
@@ -802,29 +1013,34 @@ __global__ __launch_bounds__(kBlock) void k_up_l1(
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
+    const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
     for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image<true>(img_s, lab, g, o);
-        stage_interp<T>(r_s, c_s, xc, g, o);
+        stage_image_interp<true, KM, T>(img_s, feat_s, lab, r_s, c_s, xc, g, o);
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        const int mode = choose_mode<true>(active, img_s, base, 1u, false, true);
-        const T x2 = cconv_any<T, KM, true>(mode, active, img_s, r_s, base, lz, w, wm, kst, n, idx);
+        // per-cell operands loaded ahead of the CConv (an unused A d_i slot
+        // reads x1 instead: always a valid address)
+        const T x1v = x1[idx];
+        T adv[kMaxOrtho];
+        const T* adp[kMaxOrtho] = {ad0, ad1, ad2, ad3};
+#pragma unroll
+        for (int j = 0; j < kMaxOrtho; ++j) adv[j] = (!HOOK && j < nprev ? adp[j] : x1)[idx];
+        const int mode = wave_mode<true>(wmode, tile, lz, active, img_s, base, 1u, false, true);
+        const T x2 = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) {
             T out = T(0);
-            if (img_s[base] == (uint32_t)kFluid) out = (c1 * x1[idx] + c2 * x2) * scale;
+            if (img_s[base] == (uint32_t)kFluid) out = (c1 * x1v + c2 * x2) * scale;
             dhat[idx] = out;
             if (x2out) x2out[idx] = x2;
             if (!HOOK) {
-                if (nprev > 0) v[0] += (double)out * (double)ad0[idx];
-                if (nprev > 1) v[1] += (double)out * (double)ad1[idx];
-                if (nprev > 2) v[2] += (double)out * (double)ad2[idx];
-                if (nprev > 3) v[3] += (double)out * (double)ad3[idx];
+#pragma unroll
+                for (int j = 0; j < kMaxOrtho; ++j) v[j] += j < nprev ? (double)out * (double)adv[j] : 0.0;
             }
         }
     }
@@ -848,7 +1064,7 @@ constexpr int kBottomThreads = 512;
 constexpr int kBottomLds = 2 * 640;   // >= 2 * sum of the bottom levels' cells
 
 template <class T>
-__device__ inline T bottom_get(const T* v, Grid g, int z, int y, int x) {
+__device__ __forceinline__ T bottom_get(const T* v, Grid g, int z, int y, int x) {
     return in_grid(g, z, y, x) ? v[cell_index(g, z, y, x)] : T(0);
 }
 
@@ -930,17 +1146,20 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
 // product; equal to the paper's sequential update because the directions in
 // the window are already mutually A-orthogonal), A d, and the partial dots
 // d . A d and r . d.
-template <class T>
+// NO: the number of previous-direction buffers passed (n_ortho); the first
+// nprev of them enter (state), the rest are loaded and not used.
+template <class T, int NO>
 __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ dhat,
                                                   const T* __restrict__ p0, const T* __restrict__ p1,
                                                   const T* __restrict__ p2, const T* __restrict__ p3,
                                                   const T* __restrict__ r, T* __restrict__ dout, T* __restrict__ adout,
                                                   const State* st, double* partials) {
     if (st->done) return;
-    __shared__ uint32_t lab_s[kHalo];
-    __shared__ T d_s[kHalo];
+    __shared__ uint32_t lab_s[kHaloP];
+    __shared__ T d_s[kHaloP];
     const int nprev = st->nprev;
-    const T b0 = (T)st->beta[0], b1 = (T)st->beta[1], b2 = (T)st->beta[2], b3 = (T)st->beta[3];
+    const T bj[kMaxOrtho] = {(T)st->beta[0], (T)st->beta[1], (T)st->beta[2], (T)st->beta[3]};
+    const T* pp[kMaxOrtho] = {p0, p1, p2, p3};
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
@@ -949,21 +1168,30 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         const int tile = sp.t0;
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image<true>(lab_s, lab, g, o);
-        for (int i = threadIdx.x; i < kHalo; i += kBlock) {
-            const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-            const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
-            T dv = T(0);
-            if (in_grid(g, zz, yy, xx)) {
-                const size_t q = cell_index(g, zz, yy, xx);
-                dv = dhat[q];
-                if (nprev > 0) dv -= b0 * p0[q];
-                if (nprev > 1) dv -= b1 * p1[q];
-                if (nprev > 2) dv -= b2 * p2[q];
-                if (nprev > 3) dv -= b3 * p3[q];
-            }
-            d_s[i] = dv;
-        }
+        struct LD {
+            T dh;
+            T p[NO > 0 ? NO : 1];
+            uint8_t l;
+            bool in;
+        };
+        stage_batched<kHalo, LD>(
+            [&](int i) {
+                const HaloCell c = halo_cell(g, o, i);
+                LD v;
+                v.dh = dhat[c.q];
+#pragma unroll
+                for (int j = 0; j < NO; ++j) v.p[j] = pp[j][c.q];
+                v.l = lab[c.q];
+                v.in = c.in;
+                return v;
+            },
+            [&](int i, LD v) {
+                T dv = v.dh;
+#pragma unroll
+                for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * v.p[j] : dv;
+                d_s[i] = v.in ? dv : T(0);
+                lab_s[i] = v.in ? v.l : (uint32_t)kSolid;
+            });
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         if (in_grid(g, zz, yy, xx)) {
@@ -992,8 +1220,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(size_t n, const uint8_t* __
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_laplacian(const uint8_t* __restrict__ lab, Grid g,
                                                       const T* __restrict__ x, T* __restrict__ y) {
-    __shared__ uint32_t lab_s[kHalo];
-    __shared__ T x_s[kHalo];
+    __shared__ uint32_t lab_s[kHaloP];
+    __shared__ T x_s[kHaloP];
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);

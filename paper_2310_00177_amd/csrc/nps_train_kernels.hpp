@@ -27,7 +27,7 @@ constexpr int kUStride = kBlock + 1;            // padded row of the u table in 
 // g(p) r(p + a_t) for the tile's cells (row stride kUStride), img_s the
 // haloed image.  Thread i owns sums i, i + kBlock, ...
 template <class T, bool L1>
-__device__ inline void accumulate_wgrad(const T* u_s, const uint32_t* img_s, T (&acc)[(kWGrad + kBlock - 1) / kBlock]) {
+__device__ __forceinline__ void accumulate_wgrad(const T* u_s, const uint32_t* img_s, T (&acc)[(kWGrad + kBlock - 1) / kBlock]) {
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
@@ -53,7 +53,7 @@ __device__ inline void accumulate_wgrad(const T* u_s, const uint32_t* img_s, T (
 }
 
 template <class T>
-__device__ inline void write_wgrad_partial(const T (&acc)[(kWGrad + kBlock - 1) / kBlock], double* part,
+__device__ __forceinline__ void write_wgrad_partial(const T (&acc)[(kWGrad + kBlock - 1) / kBlock], double* part,
                                            double gc1, double gc2) {
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
     double* mine = part + (size_t)blockIdx.x * kWPart;
@@ -79,10 +79,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
                                                    const T* __restrict__ x2, const T* __restrict__ k2, const State* st,
                                                    int lvl, T* __restrict__ gx1, T* __restrict__ gr2, double* part) {
     const T c1 = (T)st->c1[lvl], c2 = (T)st->c2[lvl];
-    __shared__ uint32_t img_s[kHalo];
-    __shared__ T r_s[kHalo];       // Interp(xc): the block's input
-    __shared__ T g_s[kHalo];       // gx (masked at level 1); the block's output gradient is c2 gx
-    __shared__ T c_s[kCoarseTile];
+    __shared__ uint32_t img_s[kHaloP];
+    __shared__ T r_s[kHaloP];       // Interp(xc): the block's input
+    __shared__ T g_s[kHaloP];       // gx (masked at level 1); the block's output gradient is c2 gx
+    __shared__ T c_s[kCoarseTileP];
     __shared__ T u_s[kTaps * kUStride];
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
     T acc[NO];
@@ -96,8 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
     for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const TileOrigin o = tile_origin(sp.t0, tl);
         __syncthreads();
-        stage_image<L1>(img_s, img, g, o);
-        stage_interp<T>(r_s, c_s, xc, g, o);
+        stage_image_interp<L1, kStored, T>(img_s, nullptr, img, r_s, c_s, xc, g, o);
         for (int i = threadIdx.x; i < kHalo; i += kBlock) {
             const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
             const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
@@ -158,9 +157,9 @@ template <class T, bool L1>
 __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ img, Grid g, const T* __restrict__ gx1,
                                                      const T* __restrict__ gr_next, const T* __restrict__ r1,
                                                      const T* __restrict__ k1, T* __restrict__ gr1, double* part) {
-    __shared__ uint32_t img_s[kHalo];
-    __shared__ T r_s[kHalo];
-    __shared__ T g_s[kHalo];
+    __shared__ uint32_t img_s[kHaloP];
+    __shared__ T r_s[kHaloP];
+    __shared__ T g_s[kHaloP];
     __shared__ T u_s[kTaps * kUStride];
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
     T acc[NO];
@@ -214,7 +213,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ im
 // neighbour on f's side (clamped) with 1/4, so coarse j collects f = 2j, 2j+1
 // (3/4), 2j-1, 2j+2 (1/4), and at the ends the clamped quarter of f = 0 or
 // f = 2n-1 once more.
-__device__ inline int up_adjoint_axis(int j, int nc, int* f, double* w) {
+__device__ __forceinline__ int up_adjoint_axis(int j, int nc, int* f, double* w) {
     int m = 0;
     f[m] = 2 * j; w[m++] = 0.75;
     f[m] = 2 * j + 1; w[m++] = 0.75;
@@ -337,8 +336,8 @@ template <class T>
 __global__ __launch_bounds__(kBlock) void k_train_residual(const uint8_t* __restrict__ lab, Grid g,
                                                            const T* __restrict__ b, const T* __restrict__ y,
                                                            T* __restrict__ res, double* partials) {
-    __shared__ uint32_t lab_s[kHalo];
-    __shared__ T y_s[kHalo];
+    __shared__ uint32_t lab_s[kHaloP];
+    __shared__ T y_s[kHaloP];
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
@@ -369,8 +368,8 @@ __global__ __launch_bounds__(kBlock) void k_train_residual(const uint8_t* __rest
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_train_gy(const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ res,
                                                      const State* st, T* __restrict__ gy) {
-    __shared__ uint32_t lab_s[kHalo];
-    __shared__ T r_s[kHalo];
+    __shared__ uint32_t lab_s[kHaloP];
+    __shared__ T r_s[kHaloP];
     const T inv = (T)(-1.0 / sqrt(st->rr));
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
