@@ -163,7 +163,34 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
 }
 
 int tile_grid(Grid g) { return tile_blocks(tiles_of(g).count()); }
-int red_tile_grid(Grid g) { return tile_blocks(tiles_of(g).count()); }
+
+// Grid of a pipelined tile kernel: the blocks that fit on the device at once
+// (the kernel's occupancy times the compute units), at most one per tile,
+// rounded to a multiple of kXcds; each block then walks its share of tiles.
+// Occupancy per kernel and the unit count per device are cached.
+template <class K>
+int persist_grid(K* kern, Grid g) {
+    thread_local std::unordered_map<const void*, int> occ;
+    thread_local int units[64] = {0};
+    const void* f = reinterpret_cast<const void*>(kern);
+    auto it = occ.find(f);
+    int nb = 1;
+    if (it != occ.end()) {
+        nb = it->second;
+    } else {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+        occ[f] = nb;
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (units[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1) cu = 1;
+        units[dev] = cu;
+    }
+    const long want = (long)nb * units[dev];
+    return tile_blocks((int)std::min<long>(tiles_of(g).count(), want));
+}
 int red_elem_grid(size_t n) { return red_blocks((int)std::min<size_t>((n + kBlock - 1) / kBlock, 1u << 30)); }
 int elem_grid(size_t n) { return (int)std::min<size_t>(std::max<size_t>((n + kBlock - 1) / kBlock, 1), 65536); }
 
@@ -449,10 +476,10 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         const CConvW<T>* w = cconv_block<T>(net, block_down(l));
         const MfmaW* wm = mfma_block(net, block_down(l));
         const T* kst = plan.km[l] == kStored ? cptr<T>(ws, lay.k1[l]) : nullptr;
-        const int grid = tile_grid(g);
         const double cells = (double)ncells(g);
         NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
             constexpr int KM = decltype(km)::value;
+            const int grid = persist_grid(l < L ? &k_down<T, KM, true> : &k_down<T, KM, false>, g);
             if (l < L)
                 return launch("net_down", cells, s, [&] {
                     k_down<T, KM, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, wm, kst, st,
@@ -493,9 +520,9 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         const CConvW<T>* w = cconv_block<T>(net, block_up(net, l));
         const MfmaW* wm = mfma_block(net, block_up(net, l));
         const T* kst = plan.km[l] == kStored ? cptr<T>(ws, lay.k2[l]) : nullptr;
-        const int grid = tile_grid(g);
         NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
             constexpr int KM = decltype(km)::value;
+            const int grid = persist_grid(&k_up<T, KM>, g);
             return launch("net_up", (double)ncells(g), s, [&] {
                 k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st, nullptr,
                                                     cptr<int8_t>(ws, lay.wmode[l][0]));
@@ -506,10 +533,11 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
     return NPS_OK;
 }
 
-// Level-1 down kernel.  HOOK: network only (r is the input).
+// Level-1 down kernel.  HOOK: network only (r is the input).  *nparts (if
+// given) receives its grid, the number of partials it writes.
 template <class T, class X, bool HOOK>
 int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
-                const double* b, X* xb0, X* xb1, const T* dpend, T* r, hipStream_t s) {
+                const double* b, X* xb0, X* xb1, const T* dpend, T* r, hipStream_t s, int* nparts = nullptr) {
     const Grid g = level_grid(d, 1);
     State* st = mptr<State>(ws, lay.state);
     double* partials = mptr<double>(ws, lay.partials);
@@ -518,9 +546,10 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
     const CConvW<T>* w = cconv_block<T>(net, block_down(1));
     const MfmaW* wm = mfma_block(net, block_down(1));
     const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k1[1]) : nullptr;
-    const int grid = HOOK ? tile_grid(g) : red_tile_grid(g);
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
+        const int grid = persist_grid(&k_down_l1<T, X, KM, HOOK>, g);
+        if (nparts) *nparts = grid;
         return launch("net_down_l1", (double)ncells(g), s, [&] {
             k_down_l1<T, X, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, b, xb0, xb1, dpend, r, x1, rnext, w, wm, kst, st,
                                                               partials, cptr<int8_t>(ws, lay.wmode[1][0]));
@@ -539,10 +568,10 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     const CConvW<T>* w = cconv_block<T>(net, block_up(net, 1));
     const MfmaW* wm = mfma_block(net, block_up(net, 1));
     const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k2[1]) : nullptr;
-    const int grid = HOOK ? tile_grid(g) : red_tile_grid(g);
-    if (nparts) *nparts = grid;
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
+        const int grid = persist_grid(&k_up_l1<T, KM, HOOK>, g);
+        if (nparts) *nparts = grid;
         return launch("net_up_l1", (double)ncells(g), s, [&] {
             k_up_l1<T, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, kst, st, partials, ad[0], ad[1],
                                                         ad[2], ad[3], nullptr, cptr<int8_t>(ws, lay.wmode[1][1]));
@@ -638,7 +667,7 @@ struct SolverT : Solver {
         T* r = mptr<T>(ws, lay.r);
         T* dhat = mptr<T>(ws, lay.dhat);
         const int R = o.n_ortho + 1;
-        const int rgrid = red_tile_grid(g);
+
         const int slot = k % R;
         const T* ad[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
         const T* dp[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
@@ -653,9 +682,10 @@ struct SolverT : Solver {
         T* adk = mptr<T>(ws, lay.adring[slot]);
         const T* x2 = nullptr;
         int np = 0;
-        NPS_TRY((run_down_l1<T, X, false>(net, labels, d, plan, lay, ws, b, x0, x1b, dpend, r, s)));
+        int np_down = 0;
+        NPS_TRY((run_down_l1<T, X, false>(net, labels, d, plan, lay, ws, b, x0, x1b, dpend, r, s, &np_down)));
         NPS_TRY(launch("control", 0, s, [&] {
-            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_down, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
         }));
         NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
         NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
@@ -664,9 +694,17 @@ struct SolverT : Solver {
                 k_control<kStageDots><<<1, kCtlBlock, 0, s>>>(st, partials, np, sl[0], sl[1], sl[2], sl[3], 0.0, 0.0, 0.0,
                                                                nullptr);
             }));
+        int ogrid = 0;
+        switch (o.n_ortho) {
+            case 0: ogrid = persist_grid(&k_ortho<T, 0>, g); break;
+            case 1: ogrid = persist_grid(&k_ortho<T, 1>, g); break;
+            case 2: ogrid = persist_grid(&k_ortho<T, 2>, g); break;
+            case 3: ogrid = persist_grid(&k_ortho<T, 3>, g); break;
+            default: ogrid = persist_grid(&k_ortho<T, 4>, g); break;
+        }
         NPS_TRY(launch("ortho_matvec", cells, s, [&] {
             auto go = [&](auto no) {
-                k_ortho<T, decltype(no)::value><<<rgrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r,
+                k_ortho<T, decltype(no)::value><<<ogrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r,
                                                                          dk, adk, st, partials);
             };
             switch (o.n_ortho) {
@@ -678,7 +716,7 @@ struct SolverT : Solver {
             }
         }));
         NPS_TRY(launch("control", 0, s, [&] {
-            k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, rgrid, slot, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+            k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, ogrid, slot, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
         }));
         return NPS_OK;
     }

@@ -32,6 +32,8 @@ namespace nps {
 #define NPS_WAVES_PER_EU(n) __attribute__((amdgpu_waves_per_eu(n)))
 
 // The three-piece bf16 weights of the FP32 MFMA path need more registers.
+// (The level-1 down kernel, which also keeps the next tile's two-cell halo
+// in flight, runs at 3 in every mode.)
 constexpr int waves_floor(int km) { return km == kMfmaBf16x3 ? 3 : 4; }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -116,37 +118,55 @@ __host__ __device__ constexpr int halo_off(int o) {
 __device__ __forceinline__ int halo_base(int lx, int ly, int lz) { return ((lz + 1) * HY + (ly + 1)) * HX + (lx + 1); }
 
 // Stage NH elements of a tile into LDS in two phases: get(i) only issues
-// the global loads of element i (clamped, always valid addresses, no use of
-// the loaded values, so the phase is straight-line code), then put(i, v)
-// forms and stores the elements.  Every load of the thread is in flight
-// before the first put, so the tile waits for one memory latency rather than
-// one per element.  The last, partial round reloads element NH - 1 where it
-// runs past the end and stores it past the end: the destination arrays hold
-// whole rounds (pad_block), and nothing reads the padding.
-template <int NH, class V, class Get, class Put>
-__device__ __forceinline__ void stage_batched(Get get, Put put) {
-    constexpr int K = (NH + kBlock - 1) / kBlock;
+// the global loads of element i (always valid addresses: elements outside
+// the grid read the pad constants below; no use of the loaded values, so
+// the phase is straight-line code), then put(i, v) forms and stores the
+// elements.  Every load of the thread is in flight before the first put, so
+// the tile waits for one memory latency rather than one per element.  The
+// last, partial round reloads element NH - 1 where it runs past the end and
+// stores it past the end: the destination arrays hold whole rounds
+// (pad_block), and nothing reads the padding.  load_batch / put_batch are
+// the two phases on their own, for kernels that keep the next tile's loads
+// in flight while they compute the current one.
+template <int NH, class V>
+struct Batch {
+    static constexpr int K = (NH + kBlock - 1) / kBlock;
     V v[K];
+};
+
+template <int NH, class V, class Get>
+__device__ __forceinline__ Batch<NH, V> load_batch(Get get) {
+    Batch<NH, V> bt;
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = get(min((int)threadIdx.x + k * kBlock, NH - 1));
-#pragma unroll
-    for (int k = 0; k < K; ++k) put(threadIdx.x + k * kBlock, v[k]);
+    for (int k = 0; k < Batch<NH, V>::K; ++k) bt.v[k] = get(min((int)threadIdx.x + k * kBlock, NH - 1));
+    return bt;
 }
 
-// Two stagings of one tile with all their loads in flight together.
-template <int N1, class V1, int N2, class V2, class Get1, class Put1, class Get2, class Put2>
-__device__ __forceinline__ void stage_batched2(Get1 get1, Put1 put1, Get2 get2, Put2 put2) {
-    constexpr int K1 = (N1 + kBlock - 1) / kBlock, K2 = (N2 + kBlock - 1) / kBlock;
-    V1 v1[K1];
-    V2 v2[K2];
+template <int NH, class V, class Put>
+__device__ __forceinline__ void put_batch(const Batch<NH, V>& bt, Put put) {
 #pragma unroll
-    for (int k = 0; k < K1; ++k) v1[k] = get1(min((int)threadIdx.x + k * kBlock, N1 - 1));
-#pragma unroll
-    for (int k = 0; k < K2; ++k) v2[k] = get2(min((int)threadIdx.x + k * kBlock, N2 - 1));
-#pragma unroll
-    for (int k = 0; k < K1; ++k) put1(threadIdx.x + k * kBlock, v1[k]);
-#pragma unroll
-    for (int k = 0; k < K2; ++k) put2(threadIdx.x + k * kBlock, v2[k]);
+    for (int k = 0; k < Batch<NH, V>::K; ++k) put(threadIdx.x + k * kBlock, bt.v[k]);
+}
+
+template <int NH, class V, class Get, class Put>
+__device__ __forceinline__ void stage_batched(Get get, Put put) {
+    put_batch<NH, V>(load_batch<NH, V>(get), put);
+}
+
+// What an element outside the grid reads: zero (vectors, counts) or the
+// solid label.
+__device__ const uint64_t g_pad_zero[2] = {0, 0};
+__device__ const uint8_t g_pad_solid[8] = {kSolid, kSolid, kSolid, kSolid, kSolid, kSolid, kSolid, kSolid};
+
+template <class V>
+__device__ __forceinline__ const V* pad_zero() {
+    return reinterpret_cast<const V*>(g_pad_zero);
+}
+
+// &p[q] inside the grid, else the pad.
+template <class V>
+__device__ __forceinline__ const V* at_or(const V* p, size_t q, bool in, const V* pad) {
+    return in ? p + q : pad;
 }
 
 // Grid coordinates of element i of the one-cell haloed tile.
@@ -170,30 +190,38 @@ __device__ __forceinline__ HaloCell halo_cell(Grid g, TileOrigin o, int i) {
     return HaloCell{in ? cell_index(g, z, y, x) : 0, in};
 }
 
-// The image of a level over the haloed tile.  Level 1: labels (out of grid
-// -> solid).  Coarser levels: packed counts n_fluid | n_air << 16 (out of
-// grid -> 0, i.e. solid).
-struct ImgLoad {
-    uint32_t v;
-    bool in;
-};
-
+// The image of a level at element i of the haloed tile.  Level 1: labels
+// (outside the grid: solid).  Coarser levels: packed counts n_fluid |
+// n_air << 16 (outside: 0, i.e. solid).
 template <bool L1>
-__device__ __forceinline__ ImgLoad image_load(const void* img, Grid g, TileOrigin o, int i) {
+__device__ __forceinline__ uint32_t image_load(const void* img, Grid g, TileOrigin o, int i) {
     const HaloCell c = halo_cell(g, o, i);
-    if constexpr (L1) return ImgLoad{(uint32_t)static_cast<const uint8_t*>(img)[c.q], c.in};
-    else return ImgLoad{static_cast<const uint32_t*>(img)[c.q], c.in};
-}
-
-template <bool L1>
-__device__ __forceinline__ uint32_t image_value(ImgLoad a) {
-    return a.in ? a.v : (L1 ? (uint32_t)kSolid : 0u);
+    if constexpr (L1) return *at_or(static_cast<const uint8_t*>(img), c.q, c.in, g_pad_solid);
+    else return *at_or(static_cast<const uint32_t*>(img), c.q, c.in, pad_zero<uint32_t>());
 }
 
 template <bool L1>
 __device__ __forceinline__ void stage_image(uint32_t* img_s, const void* img, Grid g, TileOrigin o) {
-    stage_batched<kHalo, ImgLoad>([&](int i) { return image_load<L1>(img, g, o, i); },
-                                  [&](int i, ImgLoad v) { img_s[i] = image_value<L1>(v); });
+    stage_batched<kHalo, uint32_t>([&](int i) { return image_load<L1>(img, g, o, i); },
+                                   [&](int i, uint32_t v) { img_s[i] = v; });
+}
+
+// Runs body(tile, pre, prefetch) over the block's tiles, where pre holds the
+// loads of the tile (load(tile), issued earlier) and prefetch() issues the
+// loads of the block's next tile into pre: the body calls it once it has
+// consumed pre and issued its own loads, so the next tile's memory latency
+// overlaps the current tile's compute.
+template <class Load, class Body>
+__device__ __forceinline__ void tile_pipeline(int ntiles, Load load, Body body) {
+    const TileSpan sp = tile_span(ntiles);
+    if (sp.t0 >= sp.t1) return;
+    auto pre = load(sp.t0);
+    for (int tile = sp.t0; tile < sp.t1; tile += sp.step) {
+        const int next = tile + sp.step;
+        body(tile, pre, [&] {
+            if (next < sp.t1) pre = load(next);
+        });
+    }
 }
 
 template <bool L1>
@@ -721,8 +749,27 @@ __device__ __forceinline__ void pool_tile_to(const T* out_s, TileOrigin o, Grid 
 // buffers and written to the other (state.xcur selects), so no block reads a
 // value another block has already updated.  HOOK (nps_apply_precond): r is
 // the input, masked to fluid.  Then x1 = CConv_1^1(r) and r^2 = Pool(x1).
+template <class X, class T>
+struct XDL {   // x, the pending direction and the label of one haloed cell
+    X x;
+    T d;
+    uint8_t l;
+};
+
+template <class T>
+struct RL {    // network input and label of one haloed cell
+    T r;
+    uint8_t l;
+};
+
+template <class X, class T>
+struct DownL1Loads {
+    Batch<kHalo2, XDL<X, T>> h2;   // two-cell halo
+    Batch<kHalo, double> b;        // b over the one-cell halo
+};
+
 template <class T, class X, int KM, bool HOOK>
-__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_down_l1(
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
     const uint8_t* __restrict__ lab, Grid g, const double* __restrict__ b, X* xb0, X* xb1,
     const T* __restrict__ dpend, T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
     const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
@@ -746,58 +793,47 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
     const int base = halo_base(lx, ly, lz);
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int tile = sp.t0;
+    auto load = [&](int tile) {
+        const TileOrigin o = tile_origin(tile, tl);
+        if constexpr (HOOK) {
+            return load_batch<kHalo, RL<T>>([&](int i) {
+                const HaloCell c = halo_cell(g, o, i);
+                return RL<T>{*at_or(r, c.q, c.in, pad_zero<T>()), *at_or(lab, c.q, c.in, g_pad_solid)};
+            });
+        } else {
+            DownL1Loads<X, T> ld;
+            ld.h2 = load_batch<kHalo2, XDL<X, T>>([&](int i) {
+                const int xx = o.x0 + i % H2X - 2, yy = o.y0 + (i / H2X) % H2Y - 2, zz = o.z0 + i / (H2X * H2Y) - 2;
+                const bool in = in_grid(g, zz, yy, xx);
+                const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
+                return XDL<X, T>{*at_or<X>(x, q, in, pad_zero<X>()), *at_or(dpend, q, in, pad_zero<T>()),
+                                 *at_or(lab, q, in, g_pad_solid)};
+            });
+            ld.b = load_batch<kHalo, double>([&](int i) {
+                const HaloCell c = halo_cell(g, o, i);
+                return *at_or(b, c.q, c.in, pad_zero<double>());
+            });
+            return ld;
+        }
+    };
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        if (HOOK) {
-            struct LR {
-                T r;
-                uint8_t l;
-                bool in;
-            };
-            stage_batched<kHalo, LR>(
-                [&](int i) {
-                    const HaloCell c = halo_cell(g, o, i);
-                    return LR{r[c.q], lab[c.q], c.in};
-                },
-                [&](int i, LR v) {
-                    r_s[i] = v.in && v.l == kFluid ? v.r : T(0);
-                    const uint32_t l = v.in ? v.l : (uint32_t)kSolid;
-                    img_s[i] = l;
-                    if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(l);
-                });
+        if constexpr (HOOK) {
+            put_batch(pre, [&](int i, RL<T> e) {
+                r_s[i] = e.l == kFluid ? e.r : T(0);
+                img_s[i] = e.l;
+                if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(e.l);
+            });
+            prefetch();
         } else {
-            // x (+ alpha d) and labels over the two-cell halo, and b over the
-            // one-cell halo, all loads in flight together
-            struct XDL {
-                X x;
-                T d;
-                uint8_t l;
-                bool in;
-            };
-            struct BL {
-                double b;
-                bool in;
-            };
-            stage_batched2<kHalo2, XDL, kHalo, BL>(
-                [&](int i) {
-                    const int xx = o.x0 + i % H2X - 2, yy = o.y0 + (i / H2X) % H2Y - 2, zz = o.z0 + i / (H2X * H2Y) - 2;
-                    const bool in = in_grid(g, zz, yy, xx);
-                    const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
-                    return XDL{x[q], dpend[q], lab[q], in};
-                },
-                [&](int i, XDL v) {
-                    X xv = v.x;
-                    if (pend) xv += alpha * (X)v.d;
-                    lab2_s[i] = v.in ? v.l : (uint8_t)kSolid;
-                    x2_s[i] = v.in ? xv : X(0);
-                },
-                [&](int i) {
-                    const HaloCell c = halo_cell(g, o, i);
-                    return BL{b[c.q], c.in};
-                },
-                [&](int i, BL v) { b_s[i] = v.in ? v.b : 0.0; });
+            // x (+ alpha d) and labels over the two-cell halo, b over the one-cell halo
+            put_batch(pre.h2, [&](int i, XDL<X, T> e) {
+                lab2_s[i] = e.l;
+                x2_s[i] = pend ? e.x + alpha * (X)e.d : e.x;
+            });
+            put_batch(pre.b, [&](int i, double bv) { b_s[i] = bv; });
+            prefetch();
             __syncthreads();
             // r = b - A x over the tile and its one-cell halo (zero off fluid /
             // off grid); the labels of the same cells become the image.
@@ -829,17 +865,22 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
         out_s[threadIdx.x] = active ? out : T(0);
         __syncthreads();
         pool_tile_to<T>(out_s, o, g, rnext);
-    }
+    });
     if (!HOOK) block_partials<kBlock>(v, partials);
 }
 
 // x1 = CConv_1(r, I) on one level l >= 2, and (POOL) r_next = Pool(x1).
+template <class T>
+struct CR {    // packed counts and network input of one haloed cell
+    uint32_t c;
+    T r;
+};
+
 template <class T, int KM, bool POOL>
-__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_down(const uint32_t* __restrict__ cnt, Grid g, uint32_t full,
-                                                 const T* __restrict__ rin, T* __restrict__ x1, T* __restrict__ rnext,
-                                                 const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm,
-                                                 const T* __restrict__ kst, const State* st,
-                                                 const int8_t* __restrict__ wmode) {
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_down(
+    const uint32_t* __restrict__ cnt, Grid g, uint32_t full, const T* __restrict__ rin, T* __restrict__ x1,
+    T* __restrict__ rnext, const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
+    const State* st, const int8_t* __restrict__ wmode) {
     if (st->done) return;
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
@@ -850,26 +891,22 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
-    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int tile = sp.t0;
+    auto load = [&](int tile) {
+        const TileOrigin o = tile_origin(tile, tl);
+        return load_batch<kHalo, CR<T>>([&](int i) {
+            const HaloCell c = halo_cell(g, o, i);
+            return CR<T>{*at_or(cnt, c.q, c.in, pad_zero<uint32_t>()), *at_or(rin, c.q, c.in, pad_zero<T>())};
+        });
+    };
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        struct CR {
-            uint32_t c;
-            T r;
-            bool in;
-        };
-        stage_batched<kHalo, CR>(
-            [&](int i) {
-                const HaloCell c = halo_cell(g, o, i);
-                return CR{cnt[c.q], rin[c.q], c.in};
-            },
-            [&](int i, CR v) {
-                const uint32_t c = v.in ? v.c : 0u;
-                img_s[i] = c;
-                if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, false>(c);
-                r_s[i] = v.in ? v.r : T(0);
-            });
+        put_batch(pre, [&](int i, CR<T> e) {
+            img_s[i] = e.c;
+            if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, false>(e.c);
+            r_s[i] = e.r;
+        });
+        prefetch();
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
@@ -882,7 +919,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
             __syncthreads();
             pool_tile_to<T>(out_s, o, g, rnext);
         }
-    }
+    });
 }
 
 // Linear 2x upsampling weights along one axis (cell-centred, edges clamped):
@@ -916,26 +953,45 @@ constexpr int CXS = TX / 2 + 4, CYS = TY / 2 + 4, CZS = TZ / 2 + 4;
 constexpr int kCoarseTile = CXS * CYS * CZS;
 constexpr int kCoarseTileP = pad_block(kCoarseTile);
 
-template <bool L1, int KM, class T>
-__device__ __forceinline__ void stage_image_interp(uint32_t* img_s, uint32_t* feat_s, const void* img, T* r_s, T* c_s,
-                                                   const T* __restrict__ xc, Grid g, TileOrigin o) {
+template <class T>
+struct UpLoads {
+    Batch<kHalo, uint32_t> img;       // image over the haloed tile
+    Batch<kCoarseTile, T> c;          // the coarse cells the tile interpolates from
+};
+
+template <bool L1, class T>
+__device__ __forceinline__ UpLoads<T> load_image_interp(const void* img, const T* __restrict__ xc, Grid g,
+                                                        TileOrigin o) {
     const Grid gc = coarser(g);
     const int bx = o.x0 / 2 - 2, by = o.y0 / 2 - 2, bz = o.z0 / 2 - 2;
-    stage_batched2<kHalo, ImgLoad, kCoarseTile, T>(
-        [&](int i) { return image_load<L1>(img, g, o, i); },
-        [&](int i, ImgLoad v) {
-            const uint32_t u = image_value<L1>(v);
-            img_s[i] = u;
-            if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, L1>(u);
-        },
-        [&](int i) {
-            const int cx = i % CXS, cy = (i / CXS) % CYS, cz = i / (CXS * CYS);
-            const int jx = min(max(bx + cx, 0), gc.nx - 1), jy = min(max(by + cy, 0), gc.ny - 1),
-                      jz = min(max(bz + cz, 0), gc.nz - 1);
-            return xc[cell_index(gc, jz, jy, jx)];
-        },
-        [&](int i, T v) { c_s[i] = v; });
-    __syncthreads();
+    UpLoads<T> u;
+    u.img = load_batch<kHalo, uint32_t>([&](int i) { return image_load<L1>(img, g, o, i); });
+    u.c = load_batch<kCoarseTile, T>([&](int i) {
+        const int cx = i % CXS, cy = (i / CXS) % CYS, cz = i / (CXS * CYS);
+        const int jx = min(max(bx + cx, 0), gc.nx - 1), jy = min(max(by + cy, 0), gc.ny - 1),
+                  jz = min(max(bz + cz, 0), gc.nz - 1);
+        return xc[cell_index(gc, jz, jy, jx)];
+    });
+    return u;
+}
+
+template <bool L1, int KM, class T>
+__device__ __forceinline__ void put_image_interp(const UpLoads<T>& u, uint32_t* img_s, uint32_t* feat_s, T* c_s) {
+    put_batch(u.img, [&](int i, uint32_t v) {
+        img_s[i] = v;
+        if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, L1>(v);
+    });
+    put_batch(u.c, [&](int i, T v) { c_s[i] = v; });
+}
+
+// Interp(xc) over the haloed tile from the staged coarse cells (zero
+// outside the level's grid: the zero padding of the CConv input).  The
+// coarse block starts two coarse cells before the tile and its coordinates
+// were clamped into the coarse grid, which is exactly the interpolation's
+// edge rule, so no further clamping is needed here.
+template <class T>
+__device__ __forceinline__ void interp_tile(T* r_s, const T* c_s, Grid g, TileOrigin o) {
+    const int bx = o.x0 / 2 - 2, by = o.y0 / 2 - 2, bz = o.z0 / 2 - 2;
     const T a = T(0.75), b = T(0.25);
     for (int i = threadIdx.x; i < kHalo; i += kBlock) {
         const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
@@ -953,6 +1009,16 @@ __device__ __forceinline__ void stage_image_interp(uint32_t* img_s, uint32_t* fe
         }
         r_s[i] = v;
     }
+}
+
+// Image and Interp(xc) of one tile in one go (for kernels that do not
+// pipeline their tiles).
+template <bool L1, int KM, class T>
+__device__ __forceinline__ void stage_image_interp(uint32_t* img_s, uint32_t* feat_s, const void* img, T* r_s, T* c_s,
+                                                   const T* __restrict__ xc, Grid g, TileOrigin o) {
+    put_image_interp<L1, KM, T>(load_image_interp<L1, T>(img, xc, g, o), img_s, feat_s, c_s);
+    __syncthreads();
+    interp_tile<T>(r_s, c_s, g, o);
 }
 
 // x = c1 x1 + c2 CConv_2(Interp(xc), I) on one level l >= 2.
@@ -974,21 +1040,24 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
-    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int tile = sp.t0;
+    auto load = [&](int tile) { return load_image_interp<false, T>(cnt, xc, g, tile_origin(tile, tl)); };
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image_interp<false, KM, T>(img_s, feat_s, cnt, r_s, c_s, xc, g, o);
-        __syncthreads();
+        put_image_interp<false, KM, T>(pre, img_s, feat_s, c_s);
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
         const T x1v = x1[idx];
+        prefetch();
+        __syncthreads();
+        interp_tile<T>(r_s, c_s, g, o);
+        __syncthreads();
         const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, tile, lz, active, img_s, base, full, false, false);
         const T x2 = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) xout[idx] = c1 * x1v + c2 * x2;
         if (active && x2out) x2out[idx] = x2;
-    }
+    });
 }
 
 // Level 1 of the up sweep: dhat = (c1 x1 + c2 CConv_2(Interp(x^2))) / ||r|| on
@@ -1015,22 +1084,25 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const int base = halo_base(lx, ly, lz);
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int tile = sp.t0;
+    const T* adp[kMaxOrtho] = {ad0, ad1, ad2, ad3};
+    auto load = [&](int tile) { return load_image_interp<true, T>(lab, xc, g, tile_origin(tile, tl)); };
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        stage_image_interp<true, KM, T>(img_s, feat_s, lab, r_s, c_s, xc, g, o);
-        __syncthreads();
+        put_image_interp<true, KM, T>(pre, img_s, feat_s, c_s);
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        // per-cell operands loaded ahead of the CConv (an unused A d_i slot
-        // reads x1 instead: always a valid address)
+        // per-cell operands, issued before the next tile's loads (an unused
+        // A d_i slot reads x1 instead: always a valid address)
         const T x1v = x1[idx];
         T adv[kMaxOrtho];
-        const T* adp[kMaxOrtho] = {ad0, ad1, ad2, ad3};
 #pragma unroll
         for (int j = 0; j < kMaxOrtho; ++j) adv[j] = (!HOOK && j < nprev ? adp[j] : x1)[idx];
+        prefetch();
+        __syncthreads();
+        interp_tile<T>(r_s, c_s, g, o);
+        __syncthreads();
         const int mode = wave_mode<true>(wmode, tile, lz, active, img_s, base, 1u, false, true);
         const T x2 = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) {
@@ -1043,7 +1115,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
                 for (int j = 0; j < kMaxOrtho; ++j) v[j] += j < nprev ? (double)out * (double)adv[j] : 0.0;
             }
         }
-    }
+    });
     if (!HOOK) block_partials<kBlock>(v, partials);
 }
 
@@ -1164,46 +1236,48 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int tile = sp.t0;
+    struct LD {
+        T dh;
+        T p[NO > 0 ? NO : 1];
+        uint8_t l;
+    };
+    auto load = [&](int tile) {
+        const TileOrigin o = tile_origin(tile, tl);
+        return load_batch<kHalo, LD>([&](int i) {
+            const HaloCell c = halo_cell(g, o, i);
+            LD e;
+            e.dh = *at_or(dhat, c.q, c.in, pad_zero<T>());
+#pragma unroll
+            for (int j = 0; j < NO; ++j) e.p[j] = *at_or(pp[j], c.q, c.in, pad_zero<T>());
+            e.l = *at_or(lab, c.q, c.in, g_pad_solid);
+            return e;
+        });
+    };
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
-        struct LD {
-            T dh;
-            T p[NO > 0 ? NO : 1];
-            uint8_t l;
-            bool in;
-        };
-        stage_batched<kHalo, LD>(
-            [&](int i) {
-                const HaloCell c = halo_cell(g, o, i);
-                LD v;
-                v.dh = dhat[c.q];
+        put_batch(pre, [&](int i, LD e) {
+            T dv = e.dh;
 #pragma unroll
-                for (int j = 0; j < NO; ++j) v.p[j] = pp[j][c.q];
-                v.l = lab[c.q];
-                v.in = c.in;
-                return v;
-            },
-            [&](int i, LD v) {
-                T dv = v.dh;
-#pragma unroll
-                for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * v.p[j] : dv;
-                d_s[i] = v.in ? dv : T(0);
-                lab_s[i] = v.in ? v.l : (uint32_t)kSolid;
-            });
-        __syncthreads();
+            for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * e.p[j] : dv;
+            d_s[i] = dv;
+            lab_s[i] = e.l;
+        });
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
-        if (in_grid(g, zz, yy, xx)) {
-            const size_t idx = cell_index(g, zz, yy, xx);
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const T rv = r[idx];
+        prefetch();
+        __syncthreads();
+        if (active) {
             const T dv = d_s[base];
             const T ad = apply_A<T, T, uint32_t>(lab_s, d_s, base, HX, HX * HY);
             dout[idx] = dv;
             adout[idx] = ad;
             v[0] += (double)dv * (double)ad;
-            v[1] += (double)r[idx] * (double)dv;
+            v[1] += (double)rv * (double)dv;
         }
-    }
+    });
     block_partials<kBlock>(v, partials);
 }
 
