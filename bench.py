@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with known-size fill and negate kernels (1 GiB each) for the HBM counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the solver-variant comparison")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations in the CPU sample")
     ap.add_argument("--serving", action="store_true",
                     help="run the request-server sweep instead (Poisson arrivals, mixed grid sizes)")
@@ -227,20 +228,20 @@ def main():
     net = nps.Net(params, 6)
     print(f"# workload {n}^3, fluid {int((lab == 0).sum())} cells", file=sys.stderr, flush=True)
 
-    def run(name, steps, warmup):
+    def run(name, steps, warmup, method=0, n_ortho=2, label=None):
         prec = prec_of[name]
-        ws = nps.workspace(lab.shape, 6, prec, 2)
+        ws = nps.workspace(lab.shape, 6, prec, n_ortho)
         x = torch.empty_like(b_d)
+        kw = dict(tol=args.tol, max_iter=args.max_iter, precision=prec, x=x, ws=ws, method=method, n_ortho=n_ortho)
         for _ in range(warmup):
-            nps.solve(net, labels_d, b_d, tol=args.tol, max_iter=args.max_iter, precision=prec, x=x, ws=ws)
+            nps.solve(net, labels_d, b_d, **kw)
         torch.cuda.synchronize()
         lat = []
         infos = []
         t0 = time.perf_counter()
         for _ in range(steps):
             s0 = time.perf_counter()
-            _, info = nps.solve(net, labels_d, b_d, tol=args.tol, max_iter=args.max_iter, precision=prec,
-                                x=x, ws=ws)
+            _, info = nps.solve(net, labels_d, b_d, **kw)
             lat.append(time.perf_counter() - s0)   # nps_solve synchronises its stream
             infos.append(info)
         torch.cuda.synchronize()
@@ -248,7 +249,7 @@ def main():
         lat_ms = np.array(lat) * 1e3
         its = [i.iterations for i in infos]
         ok = all(i.status == 0 and i.rel_residual < args.tol for i in infos)
-        print(f"# {name}: {steps / total:.2f} solves/s, {total / steps * 1e3:.2f} ms/solve, iterations {its[0]}, "
+        print(f"# {label or name}: {steps / total:.2f} solves/s, {total / steps * 1e3:.2f} ms/solve, iterations {its[0]}, "
               f"true rel residual {infos[-1].rel_residual:.2e}, converged {ok}", file=sys.stderr, flush=True)
         return {"solves_per_s": steps / total, "ms_per_solve": total / steps * 1e3,
                 "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
@@ -259,6 +260,18 @@ def main():
     comp = None
     if args.compare and args.compare not in ("none", args.headline):
         comp, _, _ = run(args.compare, args.steps, args.warmup)
+
+    # solver variants on the same system (the paper's PCG-variant and n_ortho
+    # comparisons): NPSDO with n_ortho 0..4 (0 = steepest descent), PCG, flexible PCG
+    variants = []
+    if not args.no_variants:
+        vsteps = max(2, min(args.steps, 3))
+        for method, n_ortho, tag in [(0, 0, "psd"), (0, 1, "npsdo1"), (0, 2, "npsdo2"), (0, 3, "npsdo3"),
+                                     (0, 4, "npsdo4"), (1, 1, "pcg"), (2, 1, "fpcg")]:
+            r, _, _ = run(args.headline, vsteps, 1, method=method, n_ortho=n_ortho, label=f"variant {tag}")
+            variants.append({"variant": tag, "method": ["npsdo", "pcg", "fpcg"][method], "n_ortho": n_ortho,
+                             "solves_per_s": r["solves_per_s"], "iterations": r["iterations"],
+                             "converged": r["converged"]})
 
     # profiled pass: per-kernel durations from HIP events on the launch stream
     prec = prec_of[args.headline]
@@ -330,6 +343,7 @@ def main():
                           "achieved_GBs": it_bytes / (per_iter_ms * 1e-3) / 1e9,
                           "frac": it_bytes / (per_iter_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         },
+        "variants": variants,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

@@ -61,20 +61,35 @@ enum nps_label { NPS_FLUID = 0, NPS_AIR = 1, NPS_SOLID = 2 };
  *                   residual b - A x evaluated in double.
  *   NPS_MIXED_BF16  network kernels generated on bf16 matrix cores with fp32
  *   NPS_MIXED_FP16  accumulation (fp16 for the _FP16 variant), Krylov vectors
- *                   in float, the solution accumulated in double with a
- *                   double-precision true-residual refinement every
- *                   refine_every iterations.                                 */
+ *                   in float, the solution accumulated in double and the
+ *                   residual b - A x formed in double from it every
+ *                   iteration.                                               */
 enum nps_precision { NPS_FP64 = 0, NPS_FP32 = 1, NPS_MIXED_BF16 = 2, NPS_MIXED_FP16 = 3 };
+
+/* Krylov method around the network preconditioner P (Sec. "Algorithm" and
+ * the appendix comparing PCG variants).  All three take the literal residual
+ * b - A x every iteration and apply P to r / ||r|| (P is linear in r).
+ *   NPS_NPSDO  Alg. 1: d = P(r), A-orthogonalised against the last n_ortho
+ *              directions, alpha = r.d / d.Ad (n_ortho = 0: steepest descent).
+ *   NPS_PCG    preconditioned CG: d_k = s_k + beta d_(k-1), s = P(r),
+ *              beta = r_k.s_k / r_(k-1).s_(k-1), alpha = r.s / d.Ad.
+ *   NPS_FPCG   flexible PCG: beta = s_k.(r_k - r_(k-1)) / r_(k-1).s_(k-1),
+ *              otherwise as NPS_PCG.
+ * The two PCG forms keep one previous direction: they require n_ortho = 1. */
+enum nps_method { NPS_NPSDO = 0, NPS_PCG = 1, NPS_FPCG = 2 };
 
 typedef struct { int nz, ny, nx; } nps_dims;
 
 typedef struct {
     double tol;          /* stop when ||b - A x||_2 < tol * ||b||_2 (> 0)             */
     int max_iter;        /* iteration cap (>= 0)                                      */
-    int n_ortho;         /* directions to A-orthogonalise against, 0..4 (paper: 2)    */
+    int n_ortho;         /* directions to A-orthogonalise against, 0..4 (paper: 2);  *
+                          * 1 for NPS_PCG and NPS_FPCG                                */
     int precision;       /* enum nps_precision                                        */
-    int refine_every;    /* mixed modes: FP64 refinement period (0 = only at exit)    */
+    int refine_every;    /* accepted for compatibility and ignored: the residual is   *
+                          * formed in double every iteration                          */
     int fixed_iters;     /* 1: run exactly max_iter iterations, no convergence test    */
+    int method;          /* enum nps_method (0 = NPSDO)                               */
 } nps_opts;
 
 typedef struct {

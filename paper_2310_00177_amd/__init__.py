@@ -17,11 +17,12 @@ import torch
 
 from . import _lib
 from ._lib import (NPS_FP64 as FP64, NPS_FP32 as FP32, NPS_MIXED_BF16 as MIXED_BF16,  # noqa: F401
-                   NPS_MIXED_FP16 as MIXED_FP16, STATUS_NAMES)
+                   NPS_MIXED_FP16 as MIXED_FP16, NPS_NPSDO as NPSDO, NPS_PCG as PCG, NPS_FPCG as FPCG,
+                   STATUS_NAMES)
 
 __all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "NpsError", "SolveInfo", "Server",
            "train_workspace", "net_forward", "net_backward", "train_loss", "Precond", "TrainLoss",
-           "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "workspace", "vector_dtype"]
+           "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "NPSDO", "PCG", "FPCG", "workspace", "vector_dtype"]
 
 
 class NpsError(RuntimeError):
@@ -101,13 +102,16 @@ class Net:
 
 
 def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000,
-          n_ortho: int = 2, precision: int = FP32, refine_every: int = 20, fixed_iters: bool = False,
-          x: torch.Tensor | None = None, ws: torch.Tensor | None = None, check: bool = True):
+          n_ortho: int | None = None, precision: int = FP32, refine_every: int = 0, fixed_iters: bool = False,
+          x: torch.Tensor | None = None, ws: torch.Tensor | None = None, check: bool = True, method: int = 0):
     """x, info = solve(...): labels uint8 (nz,ny,nx), b float64, both on device.
 
+    method: NPSDO (default; n_ortho defaults to 2), PCG or FPCG (n_ortho 1).
     Soft statuses (NPS_NOT_CONVERGED) are returned in info; hard errors raise
     NpsError when check is true.
     """
+    if n_ortho is None:
+        n_ortho = 2 if method == NPSDO else 1
     _check_device(labels, b)
     if labels.dtype != torch.uint8 or b.dtype != torch.float64:
         raise ValueError("labels must be uint8 and b float64")
@@ -115,7 +119,7 @@ def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, ma
         x = torch.empty_like(b)
     if ws is None:
         ws = workspace(labels.shape, net.levels, precision, n_ortho, device=labels.device)
-    opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, refine_every, 1 if fixed_iters else 0)
+    opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, refine_every, 1 if fixed_iters else 0, method)
     info = _lib.nps_info()
     ws_bytes = ws.numel() - (_aligned(ws) - ws.data_ptr())
     rc = _lib.nps_solve(net.handle, labels.data_ptr(), _dims(labels.shape), b.data_ptr(), x.data_ptr(),
@@ -176,17 +180,17 @@ class Server:
         self.handle = h
         self._shapes = {}
 
-    def request_bytes(self, shape, tol=1e-6, max_iter=1000, n_ortho=2, precision=MIXED_BF16) -> int:
-        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 0)
+    def request_bytes(self, shape, tol=1e-6, max_iter=1000, n_ortho=2, precision=MIXED_BF16, method=0) -> int:
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 0, method)
         return _lib.nps_server_request_bytes(self.handle, _dims(shape), opts)
 
     def submit(self, labels: np.ndarray, b: np.ndarray, tol: float = 1e-6, max_iter: int = 1000,
-               n_ortho: int = 2, precision: int = MIXED_BF16, fixed_iters: bool = False) -> int:
+               n_ortho: int = 2, precision: int = MIXED_BF16, fixed_iters: bool = False, method: int = 0) -> int:
         lab = np.ascontiguousarray(labels, dtype=np.uint8)
         bb = np.ascontiguousarray(b, dtype=np.float64)
         if lab.shape != bb.shape or lab.ndim != 3:
             raise ValueError("labels and b must be (nz, ny, nx) arrays of one shape")
-        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 1 if fixed_iters else 0)
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 1 if fixed_iters else 0, method)
         rc, rid = _lib.nps_server_submit(self.handle, lab.ctypes.data, _dims(lab.shape), bb.ctypes.data, opts)
         if rc != _lib.NPS_OK:
             raise NpsError(rc, "nps_server_submit")

@@ -18,6 +18,7 @@ NPS_EINVAL, NPS_ESHAPE, NPS_ELABEL, NPS_ENOFLUID = -1, -2, -3, -4
 NPS_ENONFINITE, NPS_EBREAKDOWN, NPS_ENOMEM, NPS_EDEVICE = -5, -6, -7, -8
 # enum nps_precision
 NPS_FP64, NPS_FP32, NPS_MIXED_BF16, NPS_MIXED_FP16 = 0, 1, 2, 3
+NPS_NPSDO, NPS_PCG, NPS_FPCG = 0, 1, 2
 # enum nps_label
 NPS_FLUID, NPS_AIR, NPS_SOLID = 0, 1, 2
 
@@ -33,7 +34,8 @@ class nps_dims(ctypes.Structure):
 
 class nps_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("n_ortho", ctypes.c_int),
-                ("precision", ctypes.c_int), ("refine_every", ctypes.c_int), ("fixed_iters", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("refine_every", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("method", ctypes.c_int)]
 
 
 class nps_info(ctypes.Structure):

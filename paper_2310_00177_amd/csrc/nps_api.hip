@@ -116,7 +116,7 @@ struct Layout {
     size_t x1[kMaxLevels + 1];
     size_t rb[kMaxLevels + 1];
     size_t k1[kMaxLevels + 1], k2[kMaxLevels + 1];
-    size_t dhat, dring[kRing], adring[kRing], x[2], r;
+    size_t dhat, dring[kRing], adring[kRing], x[2], r[2];
     size_t wmode[kMaxLevels + 1][2];   // per-wave CConv modes: [level][down, up (level 1)]
     size_t total;
 };
@@ -156,7 +156,8 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
         }
         L.x[0] = put(x_bytes(precision) * n);
         L.x[1] = put(x_bytes(precision) * n);
-        L.r = put(s * n);
+        L.r[0] = put(s * n);   // residuals of alternate iterations (flexible PCG reads both)
+        L.r[1] = put(s * n);
     }
     L.total = off;
     return L;
@@ -579,6 +580,16 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     });
 }
 
+int check_opts(const nps_opts& o) {
+    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NPS_EINVAL, "tol must be positive and finite");
+    if (o.max_iter < 0) return fail(NPS_EINVAL, "max_iter must be >= 0");
+    if (o.n_ortho < 0 || o.n_ortho > kMaxOrtho) return fail(NPS_EINVAL, "n_ortho must be in [0, %d]", kMaxOrtho);
+    if (o.precision < NPS_FP64 || o.precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", o.precision);
+    if (o.method < NPS_NPSDO || o.method > NPS_FPCG) return fail(NPS_EINVAL, "unknown method %d", o.method);
+    if (o.method != NPS_NPSDO && o.n_ortho != 1) return fail(NPS_EINVAL, "PCG and flexible PCG need n_ortho = 1");
+    return NPS_OK;
+}
+
 // One solve in flight, as enqueue steps on one stream: nps_solve drives a
 // single solver to completion; the request server keeps one per slot.
 struct Solver {
@@ -638,7 +649,7 @@ struct SolverT : Solver {
         X* x = mptr<X>(ws, lay.x[0]);
         const int max_iter = std::max(o.max_iter, 0);
         NPS_TRY(launch("state_init", 0, s, [&] {
-            k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho);
+            k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho, o.method);
         }));
         const int sgrid = red_elem_grid(n);
         NPS_TRY(launch("setup_scan", (double)n, s, [&] { k_scan<X><<<sgrid, kBlock, 0, s>>>(labels, b, n, x, partials); }));
@@ -664,7 +675,8 @@ struct SolverT : Solver {
         double* partials = mptr<double>(ws, lay.partials);
         X* x0 = mptr<X>(ws, lay.x[0]);
         X* x1b = mptr<X>(ws, lay.x[1]);
-        T* r = mptr<T>(ws, lay.r);
+        T* r = mptr<T>(ws, lay.r[k & 1]);
+        const T* r_prev = cptr<T>(ws, lay.r[(k + 1) & 1]);
         T* dhat = mptr<T>(ws, lay.dhat);
         const int R = o.n_ortho + 1;
 
@@ -676,6 +688,10 @@ struct SolverT : Solver {
             sl[j] = ((k - 1 - j) % R + R) % R;
             dp[j] = cptr<T>(ws, lay.dring[sl[j]]);
             ad[j] = cptr<T>(ws, lay.adring[sl[j]]);
+        }
+        if (o.method != NPS_NPSDO) {   // PCG forms: the up kernel dots P(r) with r (and r_(k-1))
+            ad[0] = r;
+            ad[1] = r_prev;
         }
         const T* dpend = cptr<T>(ws, lay.dring[((k - 1) % R + R) % R]);
         T* dk = mptr<T>(ws, lay.dring[slot]);
@@ -777,7 +793,7 @@ template <class T>
 int precond_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const T* r_in, T* d_out, void* ws,
                  const Plan& plan, const Layout& lay, hipStream_t s) {
     State* st = mptr<State>(ws, lay.state);
-    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0); }));
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0); }));
     NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
     NPS_TRY((run_down_l1<T, T, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr,
                                      const_cast<T*>(r_in), s)));
@@ -890,14 +906,6 @@ RequestLayout request_layout(nps_dims d, int levels, const nps_opts& o) {
     r.x = r.b + align256(8 * n);
     r.total = r.x + align256(8 * n);
     return r;
-}
-
-int check_opts(const nps_opts& o) {
-    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NPS_EINVAL, "tol must be positive and finite");
-    if (o.max_iter < 0) return fail(NPS_EINVAL, "max_iter must be >= 0");
-    if (o.n_ortho < 0 || o.n_ortho > kMaxOrtho) return fail(NPS_EINVAL, "n_ortho must be in [0, %d]", kMaxOrtho);
-    if (o.precision < NPS_FP64 || o.precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", o.precision);
-    return NPS_OK;
 }
 
 }  // namespace
@@ -1081,7 +1089,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
     const Layout& lay = tl.base;
     const Plan plan = make_plan(d, L, vec_bytes(NPS_FP32) == sizeof(T) ? NPS_FP32 : NPS_FP64, true);
     State* st = mptr<State>(ws, lay.state);
-    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0); }));
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0); }));
     NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
     auto img = [&](int l) -> const void* {
         return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
@@ -1345,10 +1353,7 @@ int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const 
     if (!net || !labels_d || !b_d || !x_d || !opts || !info || !ws_d) return fail(NPS_EINVAL, "null argument");
     NPS_TRY(check_dims(dims, net->levels));
     const nps_opts& o = *opts;
-    if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NPS_EINVAL, "tol must be positive and finite");
-    if (o.max_iter < 0) return fail(NPS_EINVAL, "max_iter must be >= 0");
-    if (o.n_ortho < 0 || o.n_ortho > kMaxOrtho) return fail(NPS_EINVAL, "n_ortho must be in [0, %d]", kMaxOrtho);
-    if (o.precision < NPS_FP64 || o.precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", o.precision);
+    NPS_TRY(check_opts(o));
     const Plan plan = make_plan(dims, net->levels, o.precision);
     const Layout lay = make_layout(dims, net->levels, o.precision, o.n_ortho, true);
     if (ws_bytes < lay.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);

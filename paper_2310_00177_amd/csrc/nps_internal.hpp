@@ -91,6 +91,9 @@ struct State {
     int status;                // nps_status
     int n_fluid, bad_label, nonfinite;
     int max_iter, fixed, n_ortho;
+    int method;                // nps_method
+    int ndots;                 // partial dots the level-1 up kernel forms this iteration
+    double rho, rho_prev;      // PCG forms: r . P(r)/||r|| of this and of the previous iteration
 };
 
 // Tile geometry of the stencil kernels: TX x TY x TZ cells, one per thread.

@@ -495,12 +495,13 @@ __device__ __forceinline__ Acc apply_A(const L* lab_s, const V* v_s, int base, i
 // ---------------------------------------------------------------------------
 // setup kernels
 // ---------------------------------------------------------------------------
-__global__ void k_state_init(State* st, int max_iter, int fixed, int n_ortho) {
+__global__ void k_state_init(State* st, int max_iter, int fixed, int n_ortho, int method) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         State s = {};
         s.max_iter = max_iter;
         s.fixed = fixed;
         s.n_ortho = n_ortho;
+        s.method = method;
         s.scale = 1.0;
         *st = s;
     }
@@ -686,6 +687,9 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
         st->rr = rr;
         st->scale = rr > 0.0 ? 1.0 / sqrt(rr) : 0.0;
         st->nprev = min(iter, st->n_ortho);
+        // NPSDO: d^ . A d_i per previous direction; PCG: r . d^; flexible PCG
+        // also d^ . r_(k-1)
+        st->ndots = st->method == 0 ? st->nprev : st->method == 1 ? 1 : 2;
         if (!isfinite(rr)) {
             st->done = 1;
             st->status = -6;   // NPS_EBREAKDOWN
@@ -701,8 +705,20 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
             hf->done = st->done;
         }
     } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
-        const int sl[kMaxOrtho] = {i0, i1, i2, i3};
-        for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
+        if (st->method == 0) {
+            const int sl[kMaxOrtho] = {i0, i1, i2, i3};
+            for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
+        } else {
+            // With s = P(r) = ||r|| d^ and directions kept scaled by 1/||r||,
+            // d^_k + c d^_(k-1) is parallel to s_k + beta d_(k-1) for
+            // c = beta ||r_(k-1)|| / ||r_k||: PCG c = rho_k / rho_(k-1),
+            // flexible PCG c = (rho_k - d^_k . r_(k-1)) / rho_(k-1), rho = r . d^.
+            const double rho = v[0];
+            const double num = st->method == 1 ? rho : rho - v[1];
+            st->rho = rho;
+            st->beta[0] = st->nprev > 0 ? -num / st->rho_prev : 0.0;
+            for (int j = 1; j < kMaxOrtho; ++j) st->beta[j] = 0.0;
+        }
     } else if constexpr (STAGE == kStageLoss) {     // training loss: ||b - A y||^2
         st->rr = v[0];
     } else if constexpr (STAGE == kStageStep) {     // i0: ring slot of the new direction
@@ -714,7 +730,9 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
             st->status = -6;   // NPS_EBREAKDOWN
             if (hf) hf->done = 1;
         } else {
-            st->alpha = rd / dAd;
+            // NPSDO: exact line search; PCG forms: alpha = r . s / d . A d
+            st->alpha = (st->method == 0 ? rd : st->rho) / dAd;
+            st->rho_prev = st->rho;
             st->pending = 1;
         }
     }
@@ -1061,8 +1079,9 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
 }
 
 // Level 1 of the up sweep: dhat = (c1 x1 + c2 CConv_2(Interp(x^2))) / ||r|| on
-// fluid cells (0 elsewhere), and the partial dots dhat . A d_i with the
-// stored A d_i of the previous directions.
+// fluid cells (0 elsewhere), and the state's ndots partial dots of dhat with
+// ad0.. (NPSDO: the stored A d_i of the previous directions; PCG: r; flexible
+// PCG: r and the previous residual).
 template <class T, int KM, bool HOOK>
 __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up_l1(
     const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ xc, const T* __restrict__ x1,
@@ -1077,7 +1096,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     __shared__ T c_s[kCoarseTileP];
     const T c1 = (T)st->c1[0], c2 = (T)st->c2[0];
     const T scale = HOOK ? T(1) : (T)st->scale;
-    const int nprev = HOOK ? 0 : st->nprev;
+    const int ndots = HOOK ? 0 : st->ndots;
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
@@ -1098,7 +1117,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
         const T x1v = x1[idx];
         T adv[kMaxOrtho];
 #pragma unroll
-        for (int j = 0; j < kMaxOrtho; ++j) adv[j] = (!HOOK && j < nprev ? adp[j] : x1)[idx];
+        for (int j = 0; j < kMaxOrtho; ++j) adv[j] = (!HOOK && j < ndots ? adp[j] : x1)[idx];
         prefetch();
         __syncthreads();
         interp_tile<T>(r_s, c_s, g, o);
@@ -1112,7 +1131,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
             if (x2out) x2out[idx] = x2;
             if (!HOOK) {
 #pragma unroll
-                for (int j = 0; j < kMaxOrtho; ++j) v[j] += j < nprev ? (double)out * (double)adv[j] : 0.0;
+                for (int j = 0; j < kMaxOrtho; ++j) v[j] += j < ndots ? (double)out * (double)adv[j] : 0.0;
             }
         }
     });
