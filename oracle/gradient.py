@@ -87,6 +87,31 @@ def interpolate_transpose(g: np.ndarray) -> np.ndarray:
     return out
 
 
+def transpose_apply(net: Network, g: np.ndarray) -> np.ndarray:
+    """P(I, .)^T g: the adjoint of the network in its input vector.
+
+    P is linear in r (kernels and Aff scalars depend on the image only), so
+    its adjoint is Alg. 2 run backwards with every linear step replaced by its
+    adjoint: the output restriction to fluid, c1 and c2, the transposed CConv
+    applies, the adjoints of upsampling and pooling, and the input
+    restriction to fluid.  This is the symmetric variant's second half
+    (P_sym = P^T o P, appendix on symmetry).
+    """
+    L = net.L
+    gx = np.where(net.fluid, g, 0.0)
+    gx1 = [None] * L
+    for l in range(L - 1):                       # up sweep, reversed
+        gx1[l] = net.c1[l] * gx
+        gr2 = cconv_apply_transpose(net.K2[l], net.c2[l] * gx)
+        gx = interpolate_transpose(gr2)
+    gx1[L - 1] = gx                              # coarsest: x^L = x1^L
+    gr = None
+    for l in range(L - 1, -1, -1):               # down sweep, reversed
+        gl = gx1[l] if gr is None else gx1[l] + pool_transpose(gr)
+        gr = cconv_apply_transpose(net.K1[l], gl)
+    return np.where(net.fluid, gr, 0.0)
+
+
 def loss_and_grad(params: np.ndarray, levels: int, labels: np.ndarray, b: np.ndarray):
     """(loss, gradient blob) of || b - A P(I, b) ||_2 for one system."""
     L = levels

@@ -81,3 +81,47 @@ def test_single_parameter_derivatives(problem):
         e[i] = eps
         fd = (og.loss_only(params + e, 5, lab, b) - og.loss_only(params - e, 5, lab, b)) / (2 * eps)
         assert grad[i] == pytest.approx(fd, rel=1e-4, abs=1e-8), i
+
+
+def test_transpose_apply_is_the_adjoint_of_the_network():
+    """<y, P x> = <P^T y, x> for random x, y (P from the pinned forward oracle)."""
+    lab = gi.gen_labels(gi.scene_gradcheck(), seed=8)
+    for L, params in ((5, gi.xavier_params(5, seed=2)), (4, gi.multilevel_params(4))):
+        P = onet.Network(params, L, lab)
+        rng = np.random.default_rng(L)
+        for _ in range(3):
+            x, y = rng.standard_normal(lab.shape), rng.standard_normal(lab.shape)
+            lhs = float(np.sum(y * P.apply(x)))
+            rhs = float(np.sum(og.transpose_apply(P, y) * x))
+            assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-12)
+
+
+def test_transpose_apply_matches_the_dense_transpose_on_a_tiny_grid():
+    """Brute force: P as a dense matrix from unit vectors, then transposed."""
+    lab = np.random.default_rng(3).choice(np.array([gi.FLUID, gi.AIR, gi.SOLID], np.uint8), size=(4, 4, 8),
+                                          p=[0.6, 0.2, 0.2])
+    params = gi.xavier_params(3, seed=5)
+    P = onet.Network(params, 3, lab)
+    n = lab.size
+    M = np.zeros((n, n))
+    for j in range(n):
+        e = np.zeros(n)
+        e[j] = 1.0
+        M[:, j] = P.apply(e.reshape(lab.shape)).ravel()
+    g = np.random.default_rng(1).standard_normal(n)
+    np.testing.assert_allclose(og.transpose_apply(P, g.reshape(lab.shape)).ravel(), M.T @ g, rtol=1e-11, atol=1e-12)
+
+
+def test_symmetric_variant_is_symmetric_positive():
+    """P_sym = P^T o P (appendix on symmetry): S(x, y) = 0 and x.P_sym x = |P x|^2."""
+    lab = gi.gen_labels(gi.scene_gradcheck(), seed=9)
+    P = onet.Network(gi.xavier_params(5, seed=6), 5, lab)
+
+    class Sym:
+        def apply(self, v):
+            return og.transpose_apply(P, P.apply(v))
+    rng = np.random.default_rng(4)
+    x, y = rng.standard_normal(lab.shape), rng.standard_normal(lab.shape)
+    assert onet.asymmetry(P, x, y) > 1e-3
+    assert onet.asymmetry(Sym(), x, y) < 1e-12
+    assert float(np.sum(x * Sym().apply(x))) == pytest.approx(float(np.sum(P.apply(x) ** 2)), rel=1e-12)
