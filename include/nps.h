@@ -90,6 +90,10 @@ typedef struct {
                           * formed in double every iteration                          */
     int fixed_iters;     /* 1: run exactly max_iter iterations, no convergence test    */
     int method;          /* enum nps_method (0 = NPSDO)                               */
+    int symmetric;       /* 1: precondition with P^T o P, the symmetric variant of    *
+                          * the appendix on symmetry (kernels of every level are     *
+                          * kept in the workspace; size it with                      *
+                          * nps_solve_workspace_bytes)                               */
 } nps_opts;
 
 typedef struct {
@@ -126,8 +130,13 @@ int nps_net_create(const double* params_h, size_t n_params, int levels,
 void nps_net_destroy(nps_net* net);
 int nps_net_levels(const nps_net* net);
 
-/* Workspace bytes for nps_solve / nps_apply_precond at these dims. */
+/* Workspace bytes for nps_solve / nps_apply_precond at these dims (not the
+ * symmetric variant).  0 on invalid arguments. */
 size_t nps_workspace_bytes(nps_dims dims, int levels, int precision, int n_ortho);
+
+/* Workspace bytes for nps_solve with exactly these options (any method,
+ * symmetric or not).  0 on invalid arguments. */
+size_t nps_solve_workspace_bytes(nps_dims dims, int levels, const nps_opts* opts);
 
 /* Solve A~ x~ = b~ (Alg. 1 with the network of Alg. 2 as preconditioner).
  *   labels_d  uint8[nz*ny*nx]   cell labels.
@@ -202,6 +211,24 @@ int nps_server_poll(nps_server* srv, uint64_t req_id, double* x_h, nps_info* inf
  *                     last nps_net_forward left in ws.  Not synchronised.
  * ------------------------------------------------------------------------ */
 size_t nps_train_workspace_bytes(nps_dims dims, int levels, int precision);
+
+/* y = P(I, .)^T g: the adjoint of the network in its input vector (the
+ * network is linear in it), i.e. Alg. 2 run backwards with each linear step
+ * replaced by its adjoint -- the second half of the symmetric variant
+ * P^T o P of the appendix on symmetry.  g_d, y_d: vectors of the precision's
+ * type (NPS_FP64 double, NPS_FP32 float), device, caller-owned; y is 0 off
+ * fluid.  Workspace: nps_train_workspace_bytes.  Not synchronised. */
+int nps_apply_precond_transpose(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* g_d,
+                                void* y_d, int precision, void* ws_d, size_t ws_bytes, void* stream);
+
+/* Asymmetry of the network on x, y (appendix on symmetry):
+ *   *s_h = |x.P(y) - y.P(x)| / sqrt(|x.P(x)| |y.P(y)|)   (0 if the root is 0).
+ * Also leaves P(x) in px_d and P(y) in py_d.  Vectors of the precision's
+ * vector type (double for NPS_FP64, else float), device, caller-owned; dots
+ * accumulate in double.  Workspace: nps_workspace_bytes(dims, levels,
+ * precision, 0).  Synchronises the stream (the result is a host value). */
+int nps_asymmetry(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* x_d, const void* y_d,
+                  void* px_d, void* py_d, int precision, void* ws_d, size_t ws_bytes, double* s_h, void* stream);
 int nps_net_forward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, void* y_d,
                     int precision, void* ws_d, size_t ws_bytes, void* stream);
 int nps_train_loss(const uint8_t* labels_d, nps_dims dims, int levels, const void* b_d, const void* y_d,

@@ -20,7 +20,7 @@ from ._lib import (NPS_FP64 as FP64, NPS_FP32 as FP32, NPS_MIXED_BF16 as MIXED_B
                    NPS_MIXED_FP16 as MIXED_FP16, NPS_NPSDO as NPSDO, NPS_PCG as PCG, NPS_FPCG as FPCG,
                    STATUS_NAMES)
 
-__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "NpsError", "SolveInfo", "Server",
+__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "apply_precond_transpose", "asymmetry", "NpsError", "SolveInfo", "Server",
            "train_workspace", "net_forward", "net_backward", "train_loss", "Precond", "TrainLoss",
            "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "NPSDO", "PCG", "FPCG", "workspace", "vector_dtype"]
 
@@ -103,10 +103,12 @@ class Net:
 
 def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000,
           n_ortho: int | None = None, precision: int = FP32, refine_every: int = 0, fixed_iters: bool = False,
-          x: torch.Tensor | None = None, ws: torch.Tensor | None = None, check: bool = True, method: int = 0):
+          x: torch.Tensor | None = None, ws: torch.Tensor | None = None, check: bool = True, method: int = 0,
+          symmetric: bool = False):
     """x, info = solve(...): labels uint8 (nz,ny,nx), b float64, both on device.
 
     method: NPSDO (default; n_ortho defaults to 2), PCG or FPCG (n_ortho 1).
+    symmetric: precondition with P^T o P instead of P.
     Soft statuses (NPS_NOT_CONVERGED) are returned in info; hard errors raise
     NpsError when check is true.
     """
@@ -117,9 +119,11 @@ def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, ma
         raise ValueError("labels must be uint8 and b float64")
     if x is None:
         x = torch.empty_like(b)
+    opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, refine_every, 1 if fixed_iters else 0, method,
+                         1 if symmetric else 0)
     if ws is None:
-        ws = workspace(labels.shape, net.levels, precision, n_ortho, device=labels.device)
-    opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, refine_every, 1 if fixed_iters else 0, method)
+        nbytes = _lib.nps_solve_workspace_bytes(_dims(labels.shape), net.levels, opts)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=labels.device)
     info = _lib.nps_info()
     ws_bytes = ws.numel() - (_aligned(ws) - ws.data_ptr())
     rc = _lib.nps_solve(net.handle, labels.data_ptr(), _dims(labels.shape), b.data_ptr(), x.data_ptr(),
@@ -163,6 +167,43 @@ def apply_precond(net: Net, labels: torch.Tensor, r: torch.Tensor, precision: in
     return d
 
 
+def apply_precond_transpose(net: Net, labels: torch.Tensor, g: torch.Tensor,
+                            ws: torch.Tensor | None = None) -> torch.Tensor:
+    """y = P(I, .)^T g (float64 or float32 vectors)."""
+    _check_device(labels, g)
+    prec = FP64 if g.dtype == torch.float64 else FP32
+    if g.dtype not in (torch.float64, torch.float32):
+        raise ValueError("g must be float64 or float32")
+    if ws is None:
+        ws = train_workspace(labels.shape, net.levels, prec, device=labels.device)
+    y = torch.empty_like(g)
+    wp, wb = _ws_args(ws)
+    rc = _lib.nps_apply_precond_transpose(net.handle, labels.data_ptr(), _dims(labels.shape), g.data_ptr(),
+                                          y.data_ptr(), prec, wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_apply_precond_transpose")
+    return y
+
+
+def asymmetry(net: Net, labels: torch.Tensor, x: torch.Tensor, y: torch.Tensor, precision: int | None = None,
+              ws: torch.Tensor | None = None) -> float:
+    """S(x, y) = |x.P(y) - y.P(x)| / sqrt(|x.P(x)| |y.P(y)|) on the GPU."""
+    _check_device(labels, x)
+    if precision is None:
+        precision = FP64 if x.dtype == torch.float64 else FP32
+    if x.dtype != vector_dtype(precision) or y.dtype != x.dtype:
+        raise ValueError(f"x and y must be {vector_dtype(precision)} for precision {precision}")
+    if ws is None:
+        ws = workspace(labels.shape, net.levels, precision, 0, device=labels.device)
+    px, py = torch.empty_like(x), torch.empty_like(y)
+    wp, wb = _ws_args(ws)
+    rc, val = _lib.nps_asymmetry(net.handle, labels.data_ptr(), _dims(labels.shape), x.data_ptr(), y.data_ptr(),
+                                 px.data_ptr(), py.data_ptr(), precision, wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_asymmetry")
+    return val
+
+
 class Server:
     """Continuous-batching request server (nps_server_* in the C ABI).
 
@@ -181,7 +222,7 @@ class Server:
         self._shapes = {}
 
     def request_bytes(self, shape, tol=1e-6, max_iter=1000, n_ortho=2, precision=MIXED_BF16, method=0) -> int:
-        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 0, method)
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 0, method, 0)
         return _lib.nps_server_request_bytes(self.handle, _dims(shape), opts)
 
     def submit(self, labels: np.ndarray, b: np.ndarray, tol: float = 1e-6, max_iter: int = 1000,
@@ -190,7 +231,7 @@ class Server:
         bb = np.ascontiguousarray(b, dtype=np.float64)
         if lab.shape != bb.shape or lab.ndim != 3:
             raise ValueError("labels and b must be (nz, ny, nx) arrays of one shape")
-        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 1 if fixed_iters else 0, method)
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 1 if fixed_iters else 0, method, 0)
         rc, rid = _lib.nps_server_submit(self.handle, lab.ctypes.data, _dims(lab.shape), bb.ctypes.data, opts)
         if rc != _lib.NPS_OK:
             raise NpsError(rc, "nps_server_submit")

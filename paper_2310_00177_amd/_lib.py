@@ -35,7 +35,7 @@ class nps_dims(ctypes.Structure):
 class nps_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("n_ortho", ctypes.c_int),
                 ("precision", ctypes.c_int), ("refine_every", ctypes.c_int), ("fixed_iters", ctypes.c_int),
-                ("method", ctypes.c_int)]
+                ("method", ctypes.c_int), ("symmetric", ctypes.c_int)]
 
 
 class nps_info(ctypes.Structure):
@@ -61,6 +61,13 @@ _lib.nps_net_create.restype = _int
 _lib.nps_net_destroy.argtypes, _lib.nps_net_destroy.restype = [_vp], None
 _lib.nps_net_levels.argtypes, _lib.nps_net_levels.restype = [_vp], _int
 _lib.nps_workspace_bytes.argtypes, _lib.nps_workspace_bytes.restype = [nps_dims, _int, _int, _int], _sz
+_lib.nps_solve_workspace_bytes.argtypes = [nps_dims, _int, ctypes.POINTER(nps_opts)]
+_lib.nps_solve_workspace_bytes.restype = _sz
+_lib.nps_apply_precond_transpose.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _int, _vp, _sz, _vp]
+_lib.nps_apply_precond_transpose.restype = _int
+_lib.nps_asymmetry.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _vp, _vp, _int, _vp, _sz, ctypes.POINTER(ctypes.c_double),
+                               _vp]
+_lib.nps_asymmetry.restype = _int
 _lib.nps_solve.argtypes = [_vp, _vp, nps_dims, _vp, _vp, ctypes.POINTER(nps_opts), ctypes.POINTER(nps_info),
                            _vp, _sz, _vp]
 _lib.nps_solve.restype = _int
@@ -94,7 +101,8 @@ _lib.nps_profile_read.restype = _int
 _lib.nps_last_error.argtypes, _lib.nps_last_error.restype = [], ctypes.c_char_p
 
 EXPORTED = ["nps_param_count", "nps_net_bytes", "nps_net_create", "nps_net_destroy", "nps_net_levels",
-            "nps_workspace_bytes", "nps_solve", "nps_apply_laplacian", "nps_apply_precond", "nps_server_create",
+            "nps_workspace_bytes", "nps_solve_workspace_bytes", "nps_solve", "nps_apply_laplacian",
+            "nps_apply_precond", "nps_apply_precond_transpose", "nps_asymmetry", "nps_server_create",
             "nps_server_destroy", "nps_server_request_bytes", "nps_server_submit", "nps_server_step",
             "nps_server_poll", "nps_train_workspace_bytes", "nps_net_forward", "nps_train_loss", "nps_net_backward",
             "nps_profile_enable", "nps_profile_read", "nps_last_error"]
@@ -127,6 +135,24 @@ def nps_net_levels(net: int) -> int:
 
 def nps_workspace_bytes(dims: nps_dims, levels: int, precision: int, n_ortho: int) -> int:
     return _lib.nps_workspace_bytes(dims, levels, precision, n_ortho)
+
+
+def nps_solve_workspace_bytes(dims: nps_dims, levels: int, opts: nps_opts) -> int:
+    return _lib.nps_solve_workspace_bytes(dims, levels, ctypes.byref(opts))
+
+
+def nps_apply_precond_transpose(net: int, labels_d: int, dims: nps_dims, g_d: int, y_d: int, precision: int,
+                                ws_d: int, ws_bytes: int, stream: int) -> int:
+    return _lib.nps_apply_precond_transpose(net, labels_d, dims, g_d, y_d, precision, ws_d, ws_bytes, stream)
+
+
+def nps_asymmetry(net: int, labels_d: int, dims: nps_dims, x_d: int, y_d: int, px_d: int, py_d: int,
+                  precision: int, ws_d: int, ws_bytes: int, stream: int) -> tuple:
+    """Returns (status, S)."""
+    out = ctypes.c_double()
+    rc = _lib.nps_asymmetry(net, labels_d, dims, x_d, y_d, px_d, py_d, precision, ws_d, ws_bytes,
+                            ctypes.byref(out), stream)
+    return rc, out.value
 
 
 def nps_solve(net: int, labels_d: int, dims: nps_dims, b_d: int, x_d: int, opts: nps_opts,

@@ -163,6 +163,51 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
     return L;
 }
 
+// Training (and symmetric-variant) workspace: the base layout with stored
+// kernels at every level, plus the adjoint sweep's per-level gradients.
+struct TrainLayout {
+    Layout base;                 // state, partials, counts, x1, rb (= down inputs), stored K
+    size_t xup[kMaxLevels + 1], x2[kMaxLevels + 1];
+    size_t gx[kMaxLevels + 1], gx1[kMaxLevels + 1], gr1[kMaxLevels + 1], gr2[kMaxLevels + 1];
+    size_t wpart, spart, dc, res;
+    size_t dsym;                 // solve with P^T o P: the direction after P^T
+    size_t total;
+};
+
+constexpr int kSumBlocks = 256;   // grid of k_image_sums
+
+TrainLayout make_train_layout(nps_dims d, int levels, int precision, bool solve = false, int n_ortho = 0) {
+    TrainLayout t = {};
+    t.base = make_layout(d, levels, precision, n_ortho, solve, true);
+    size_t off = t.base.total;
+    auto put = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    const size_t s = vec_bytes(precision);
+    for (int l = 1; l <= levels; ++l) {
+        const size_t nl = ncells(level_grid(d, l));
+        if (l >= 2 && l < levels) t.xup[l] = put(s * nl);
+        if (l < levels) {
+            t.x2[l] = put(s * nl);
+            t.gx1[l] = put(s * nl);
+            t.gr2[l] = put(s * nl);
+        }
+        if (l >= 2) {
+            t.gx[l] = put(s * nl);
+            t.gr1[l] = put(s * nl);
+        }
+    }
+    t.wpart = put(sizeof(double) * kWPart * kTrainBlocks);
+    t.spart = put(sizeof(double) * 3 * kTaps * kSumBlocks * levels);
+    t.dc = put(sizeof(double) * 2 * levels);
+    t.res = put(s * ncells(level_grid(d, 1)));
+    if (solve) t.dsym = put(s * ncells(level_grid(d, 1)));
+    t.total = off;
+    return t;
+}
+
 int tile_grid(Grid g) { return tile_blocks(tiles_of(g).count()); }
 
 // Grid of a pipelined tile kernel: the blocks that fit on the device at once
@@ -580,6 +625,61 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     });
 }
 
+// y = P^T g, the adjoint of the network in its input vector (P is linear in
+// it): Alg. 2 backwards with each linear step replaced by its adjoint, on
+// the stored kernels of every level (the setup of the layout tl must have
+// run).  g and y are level-1 vectors; tl's gradient buffers are scratch.
+template <class T>
+int adjoint_apply(const nps_net* net, const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws,
+                  const T* g_in, T* y, hipStream_t s) {
+    const int L = net->levels;
+    const Layout& lay = tl.base;
+    const State* st = cptr<State>(ws, lay.state);
+    auto img = [&](int l) -> const void* {
+        return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
+    };
+    for (int l = 1; l < L; ++l) {   // up sweep, reversed
+        const Grid g = level_grid(d, l);
+        const int grid = tile_grid(g);
+        const T* gin = l == 1 ? g_in : cptr<T>(ws, tl.gx[l]);
+        const T* k2 = cptr<T>(ws, lay.k2[l]);
+        T* gx1 = mptr<T>(ws, tl.gx1[l]);
+        T* gr2 = mptr<T>(ws, tl.gr2[l]);
+        if (l == 1)
+            NPS_TRY(launch("adj_up", (double)ncells(g), s, [&] {
+                k_bwd_up<T, true, false><<<grid, kBlock, 0, s>>>(img(l), g, gin, nullptr, nullptr, nullptr, k2, st, l - 1,
+                                                                 gx1, gr2, nullptr);
+            }));
+        else
+            NPS_TRY(launch("adj_up", (double)ncells(g), s, [&] {
+                k_bwd_up<T, false, false><<<grid, kBlock, 0, s>>>(img(l), g, gin, nullptr, nullptr, nullptr, k2, st, l - 1,
+                                                                  gx1, gr2, nullptr);
+            }));
+        const Grid gc = level_grid(d, l + 1);
+        T* gxc = mptr<T>(ws, tl.gx[l + 1]);
+        NPS_TRY(launch("adj_interp", (double)ncells(gc), s, [&] {
+            k_bwd_interp<T><<<elem_grid(ncells(gc)), kBlock, 0, s>>>(gc, gr2, gxc);
+        }));
+    }
+    for (int l = L; l >= 1; --l) {   // down sweep, reversed (the coarsest output gradient is gx^L)
+        const Grid g = level_grid(d, l);
+        const int grid = tile_grid(g);
+        const T* gx1 = l == L ? cptr<T>(ws, tl.gx[L]) : cptr<T>(ws, tl.gx1[l]);
+        const T* gr_next = l < L ? cptr<T>(ws, tl.gr1[l + 1]) : nullptr;
+        const T* k1 = cptr<T>(ws, lay.k1[l]);
+        T* gr1 = l > 1 ? mptr<T>(ws, tl.gr1[l]) : y;
+        if (l == 1)
+            NPS_TRY(launch("adj_down", (double)ncells(g), s, [&] {
+                k_bwd_down<T, true, false><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, nullptr, k1, gr1, nullptr);
+            }));
+        else
+            NPS_TRY(launch("adj_down", (double)ncells(g), s, [&] {
+                k_bwd_down<T, false, false><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, nullptr, k1, gr1, nullptr);
+            }));
+    }
+    return NPS_OK;
+}
+
 int check_opts(const nps_opts& o) {
     if (!(o.tol > 0.0) || !std::isfinite(o.tol)) return fail(NPS_EINVAL, "tol must be positive and finite");
     if (o.max_iter < 0) return fail(NPS_EINVAL, "max_iter must be >= 0");
@@ -587,7 +687,33 @@ int check_opts(const nps_opts& o) {
     if (o.precision < NPS_FP64 || o.precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", o.precision);
     if (o.method < NPS_NPSDO || o.method > NPS_FPCG) return fail(NPS_EINVAL, "unknown method %d", o.method);
     if (o.method != NPS_NPSDO && o.n_ortho != 1) return fail(NPS_EINVAL, "PCG and flexible PCG need n_ortho = 1");
+    if (o.symmetric != 0 && o.symmetric != 1) return fail(NPS_EINVAL, "symmetric must be 0 or 1");
     return NPS_OK;
+}
+
+// Plan and workspace layout of a solve: the symmetric variant keeps the
+// kernels of every level in HBM (its P^T sweep gathers them) and carries the
+// adjoint's buffers.
+struct SolveLayout {
+    Plan plan;
+    Layout lay;
+    TrainLayout tl;
+    size_t total;
+};
+
+SolveLayout solve_layout(nps_dims d, int levels, const nps_opts& o) {
+    SolveLayout r{};
+    if (o.symmetric) {
+        r.plan = make_plan(d, levels, o.precision, true);
+        r.tl = make_train_layout(d, levels, o.precision, true, o.n_ortho);
+        r.lay = r.tl.base;
+        r.total = r.tl.total;
+    } else {
+        r.plan = make_plan(d, levels, o.precision);
+        r.lay = make_layout(d, levels, o.precision, o.n_ortho, true);
+        r.total = r.lay.total;
+    }
+    return r;
 }
 
 // One solve in flight, as enqueue steps on one stream: nps_solve drives a
@@ -600,6 +726,7 @@ struct Solver {
     nps_opts o{};
     Plan plan{};
     Layout lay{};
+    TrainLayout tl{};             // symmetric variant only
     void* ws = nullptr;
     hipStream_t s = nullptr;
     State* hs = nullptr;          // pinned host mirror of the device state
@@ -649,7 +776,7 @@ struct SolverT : Solver {
         X* x = mptr<X>(ws, lay.x[0]);
         const int max_iter = std::max(o.max_iter, 0);
         NPS_TRY(launch("state_init", 0, s, [&] {
-            k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho, o.method);
+            k_state_init<<<1, 64, 0, s>>>(st, max_iter, o.fixed_iters ? 1 : 0, o.n_ortho, o.method, o.symmetric);
         }));
         const int sgrid = red_elem_grid(n);
         NPS_TRY(launch("setup_scan", (double)n, s, [&] { k_scan<X><<<sgrid, kBlock, 0, s>>>(labels, b, n, x, partials); }));
@@ -705,6 +832,16 @@ struct SolverT : Solver {
         }));
         NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
         NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
+        if (o.symmetric) {   // d^ = P^T P(r)/||r||, then the dots the up kernel left out
+            T* dsym = mptr<T>(ws, tl.dsym);
+            NPS_TRY(adjoint_apply<T>(net, labels, d, tl, ws, dhat, dsym, s));
+            const size_t n = ncells(g);
+            np = red_elem_grid(n);
+            NPS_TRY(launch("sym_dots", cells, s, [&] {
+                k_dots<T><<<np, kBlock, 0, s>>>(n, dsym, ad[0], ad[1], ad[2], ad[3], st, partials);
+            }));
+            dhat = dsym;
+        }
         if (o.n_ortho > 0)
             NPS_TRY(launch("control", 0, s, [&] {
                 k_control<kStageDots><<<1, kCtlBlock, 0, s>>>(st, partials, np, sl[0], sl[1], sl[2], sl[3], 0.0, 0.0, 0.0,
@@ -793,7 +930,7 @@ template <class T>
 int precond_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const T* r_in, T* d_out, void* ws,
                  const Plan& plan, const Layout& lay, hipStream_t s) {
     State* st = mptr<State>(ws, lay.state);
-    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0); }));
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0, 0); }));
     NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
     NPS_TRY((run_down_l1<T, T, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr,
                                      const_cast<T*>(r_in), s)));
@@ -901,7 +1038,7 @@ RequestLayout request_layout(nps_dims d, int levels, const nps_opts& o) {
     RequestLayout r{};
     const size_t n = ncells(level_grid(d, 1));
     r.ws = 0;
-    r.lab = align256(make_layout(d, levels, o.precision, o.n_ortho, true).total);
+    r.lab = align256(solve_layout(d, levels, o).total);
     r.b = r.lab + align256(n);
     r.x = r.b + align256(8 * n);
     r.total = r.x + align256(8 * n);
@@ -954,8 +1091,10 @@ int admit(nps_server* srv, Slot& sl, Request* r) {
     sv->b = reinterpret_cast<const double*>(base + rl.b);
     sv->d = r->d;
     sv->o = r->o;
-    sv->plan = make_plan(r->d, srv->net->levels, r->o.precision);
-    sv->lay = make_layout(r->d, srv->net->levels, r->o.precision, r->o.n_ortho, true);
+    const SolveLayout sol = solve_layout(r->d, srv->net->levels, r->o);
+    sv->plan = sol.plan;
+    sv->lay = sol.lay;
+    sv->tl = sol.tl;
     sv->ws = base + rl.ws;
     sv->s = sl.s;
     sv->hs = sl.hs;
@@ -1037,47 +1176,6 @@ int advance(nps_server* srv, Slot& sl) {
 // ---------------------------------------------------------------------------
 // training: forward with saved activations, backward, loss
 // ---------------------------------------------------------------------------
-struct TrainLayout {
-    Layout base;                 // state, partials, counts, x1, rb (= down inputs), stored K
-    size_t xup[kMaxLevels + 1], x2[kMaxLevels + 1];
-    size_t gx[kMaxLevels + 1], gx1[kMaxLevels + 1], gr1[kMaxLevels + 1], gr2[kMaxLevels + 1];
-    size_t wpart, spart, dc, res;
-    size_t total;
-};
-
-constexpr int kSumBlocks = 256;   // grid of k_image_sums
-
-TrainLayout make_train_layout(nps_dims d, int levels, int precision) {
-    TrainLayout t = {};
-    t.base = make_layout(d, levels, precision, 0, false, true);
-    size_t off = t.base.total;
-    auto put = [&](size_t bytes) {
-        const size_t at = off;
-        off += align256(bytes);
-        return at;
-    };
-    const size_t s = vec_bytes(precision);
-    for (int l = 1; l <= levels; ++l) {
-        const size_t nl = ncells(level_grid(d, l));
-        if (l >= 2 && l < levels) t.xup[l] = put(s * nl);
-        if (l < levels) {
-            t.x2[l] = put(s * nl);
-            t.gx1[l] = put(s * nl);
-            t.gr2[l] = put(s * nl);
-        }
-        if (l >= 2) {
-            t.gx[l] = put(s * nl);
-            t.gr1[l] = put(s * nl);
-        }
-    }
-    t.wpart = put(sizeof(double) * kWPart * kTrainBlocks);
-    t.spart = put(sizeof(double) * 3 * kTaps * kSumBlocks * levels);
-    t.dc = put(sizeof(double) * 2 * levels);
-    t.res = put(s * ncells(level_grid(d, 1)));
-    t.total = off;
-    return t;
-}
-
 size_t off_c1(int l) { return (size_t)(l - 1) * (27 * 81 + 27); }
 size_t off_c2(int L, int l) { return (size_t)(L + l - 1) * (27 * 81 + 27); }
 size_t off_aff(int L, int l) { return (size_t)(2 * L - 1) * (27 * 81 + 27) + (size_t)(l - 1) * 164; }
@@ -1089,7 +1187,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
     const Layout& lay = tl.base;
     const Plan plan = make_plan(d, L, vec_bytes(NPS_FP32) == sizeof(T) ? NPS_FP32 : NPS_FP64, true);
     State* st = mptr<State>(ws, lay.state);
-    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0); }));
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0, 0); }));
     NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
     auto img = [&](int l) -> const void* {
         return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
@@ -1182,11 +1280,11 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
         T* gr2 = mptr<T>(ws, tl.gr2[l]);
         if (l == 1)
             NPS_TRY(launch("train_bwd_up", (double)ncells(g), s, [&] {
-                k_bwd_up<T, true><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
+                k_bwd_up<T, true, true><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
             }));
         else
             NPS_TRY(launch("train_bwd_up", (double)ncells(g), s, [&] {
-                k_bwd_up<T, false><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
+                k_bwd_up<T, false, true><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
             }));
         const double scale = std::ldexp(1.0, -3 * (l - 1));
         double* gW = grad + off_c2(L, l);
@@ -1215,11 +1313,11 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
         T* gr1 = l > 1 ? mptr<T>(ws, tl.gr1[l]) : nullptr;
         if (l == 1)
             NPS_TRY(launch("train_bwd_down", (double)ncells(g), s, [&] {
-                k_bwd_down<T, true><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
+                k_bwd_down<T, true, true><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
             }));
         else
             NPS_TRY(launch("train_bwd_down", (double)ncells(g), s, [&] {
-                k_bwd_down<T, false><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
+                k_bwd_down<T, false, true><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
             }));
         const double scale = std::ldexp(1.0, -3 * (l - 1));
         double* gW = grad + off_c1(l);
@@ -1348,15 +1446,19 @@ size_t nps_workspace_bytes(nps_dims dims, int levels, int precision, int n_ortho
     return make_layout(dims, levels, precision, n_ortho, true).total;
 }
 
+size_t nps_solve_workspace_bytes(nps_dims dims, int levels, const nps_opts* opts) {
+    if (!opts || check_dims(dims, levels) != NPS_OK || check_opts(*opts) != NPS_OK) return 0;
+    return solve_layout(dims, levels, *opts).total;
+}
+
 int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const double* b_d, double* x_d,
               const nps_opts* opts, nps_info* info, void* ws_d, size_t ws_bytes, void* stream) {
     if (!net || !labels_d || !b_d || !x_d || !opts || !info || !ws_d) return fail(NPS_EINVAL, "null argument");
     NPS_TRY(check_dims(dims, net->levels));
     const nps_opts& o = *opts;
     NPS_TRY(check_opts(o));
-    const Plan plan = make_plan(dims, net->levels, o.precision);
-    const Layout lay = make_layout(dims, net->levels, o.precision, o.n_ortho, true);
-    if (ws_bytes < lay.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total);
+    const SolveLayout sl = solve_layout(dims, net->levels, o);
+    if (ws_bytes < sl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, sl.total);
     if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
     std::memset(info, 0, sizeof(*info));
     HostMirror* hm = host_mirror();
@@ -1367,8 +1469,9 @@ int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const 
     sv->b = b_d;
     sv->d = dims;
     sv->o = o;
-    sv->plan = plan;
-    sv->lay = lay;
+    sv->plan = sl.plan;
+    sv->lay = sl.lay;
+    sv->tl = sl.tl;
     sv->ws = ws_d;
     sv->s = static_cast<hipStream_t>(stream);
     sv->hs = hm->state;
@@ -1466,6 +1569,62 @@ int nps_train_loss(const uint8_t* labels_d, nps_dims dims, int levels, const voi
                                   static_cast<double*>(gy_d), loss_h, s);
     return train_loss<float>(labels_d, dims, tl, ws_d, static_cast<const float*>(b_d), static_cast<const float*>(y_d),
                              static_cast<float*>(gy_d), loss_h, s);
+}
+
+int nps_apply_precond_transpose(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* g_d,
+                                void* y_d, int precision, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!net || !labels_d || !g_d || !y_d || !ws_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "precision must be FP64 or FP32");
+    const TrainLayout tl = make_train_layout(dims, net->levels, precision);
+    if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Plan plan = make_plan(dims, net->levels, precision, true);
+    State* st = mptr<State>(ws_d, tl.base.state);
+    NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0, 0); }));
+    if (precision == NPS_FP64) {
+        NPS_TRY(run_setup<double>(net, labels_d, dims, plan, tl.base, ws_d, s));
+        return adjoint_apply<double>(net, labels_d, dims, tl, ws_d, static_cast<const double*>(g_d),
+                                     static_cast<double*>(y_d), s);
+    }
+    NPS_TRY(run_setup<float>(net, labels_d, dims, plan, tl.base, ws_d, s));
+    return adjoint_apply<float>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(g_d), static_cast<float*>(y_d),
+                                s);
+}
+
+int nps_asymmetry(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* x_d, const void* y_d,
+                  void* px_d, void* py_d, int precision, void* ws_d, size_t ws_bytes, double* s_h, void* stream) {
+    if (!net || !labels_d || !x_d || !y_d || !px_d || !py_d || !ws_d || !s_h) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (precision < NPS_FP64 || precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", precision);
+    const Plan plan = make_plan(dims, net->levels, precision);
+    const Layout lay = make_layout(dims, net->levels, precision, 0, false);
+    if (ws_bytes < lay.total + 256) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, lay.total + 256);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t n = ncells(level_grid(dims, 1));
+    double* partials = mptr<double>(ws_d, lay.partials);
+    double* sums = mptr<double>(ws_d, lay.total);   // 4 doubles past the layout
+    const int grid = red_elem_grid(n);
+    auto run = [&](auto tag) -> int {
+        using T = decltype(tag);
+        NPS_TRY(precond_impl<T>(net, labels_d, dims, static_cast<const T*>(x_d), static_cast<T*>(px_d), ws_d, plan, lay, s));
+        NPS_TRY(precond_impl<T>(net, labels_d, dims, static_cast<const T*>(y_d), static_cast<T*>(py_d), ws_d, plan, lay, s));
+        NPS_TRY(launch("asym_dots", (double)n, s, [&] {
+            k_dot4<T><<<grid, kBlock, 0, s>>>(n, static_cast<const T*>(x_d), static_cast<const T*>(y_d),
+                                              static_cast<const T*>(px_d), static_cast<const T*>(py_d), partials);
+        }));
+        return NPS_OK;
+    };
+    NPS_TRY(precision == NPS_FP64 ? run(0.0) : run(0.0f));
+    NPS_TRY(launch("asym_sum", 0, s, [&] { k_sum_partials<<<1, kBlock, 0, s>>>(partials, grid, sums); }));
+    double v[4];
+    NPS_HIP(hipMemcpyAsync(v, sums, sizeof(v), hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipStreamSynchronize(s));
+    const double den = std::sqrt(std::fabs(v[2]) * std::fabs(v[3]));
+    *s_h = den > 0.0 ? std::fabs(v[0] - v[1]) / den : 0.0;
+    return NPS_OK;
 }
 
 int nps_profile_enable(int on) {

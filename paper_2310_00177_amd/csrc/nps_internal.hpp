@@ -92,6 +92,7 @@ struct State {
     int n_fluid, bad_label, nonfinite;
     int max_iter, fixed, n_ortho;
     int method;                // nps_method
+    int sym;                   // 1: preconditioner P^T o P (the symmetric variant)
     int ndots;                 // partial dots the level-1 up kernel forms this iteration
     double rho, rho_prev;      // PCG forms: r . P(r)/||r|| of this and of the previous iteration
 };

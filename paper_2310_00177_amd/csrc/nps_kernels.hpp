@@ -495,13 +495,14 @@ __device__ __forceinline__ Acc apply_A(const L* lab_s, const V* v_s, int base, i
 // ---------------------------------------------------------------------------
 // setup kernels
 // ---------------------------------------------------------------------------
-__global__ void k_state_init(State* st, int max_iter, int fixed, int n_ortho, int method) {
+__global__ void k_state_init(State* st, int max_iter, int fixed, int n_ortho, int method, int sym) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         State s = {};
         s.max_iter = max_iter;
         s.fixed = fixed;
         s.n_ortho = n_ortho;
         s.method = method;
+        s.sym = sym;
         s.scale = 1.0;
         *st = s;
     }
@@ -1096,7 +1097,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     __shared__ T c_s[kCoarseTileP];
     const T c1 = (T)st->c1[0], c2 = (T)st->c2[0];
     const T scale = HOOK ? T(1) : (T)st->scale;
-    const int ndots = HOOK ? 0 : st->ndots;
+    const int ndots = HOOK || st->sym ? 0 : st->ndots;   // the symmetric variant dots after P^T
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
@@ -1298,6 +1299,63 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         }
     });
     block_partials<kBlock>(v, partials);
+}
+
+// Partial dots v . a_j, j < the state's ndots (the up kernel's dots, for the
+// symmetric variant whose direction is formed after P^T); an unused slot
+// reads v itself.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dots(size_t n, const T* __restrict__ v, const T* __restrict__ a0,
+                                                 const T* __restrict__ a1, const T* __restrict__ a2,
+                                                 const T* __restrict__ a3, const State* st, double* partials) {
+    if (st->done) return;
+    const int nd = st->ndots;
+    const T* ap[kMaxOrtho] = {nd > 0 ? a0 : v, nd > 1 ? a1 : v, nd > 2 ? a2 : v, nd > 3 ? a3 : v};
+    double acc[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const double vi = (double)v[i];
+#pragma unroll
+        for (int j = 0; j < kMaxOrtho; ++j) acc[j] += j < nd ? vi * (double)ap[j][i] : 0.0;
+    }
+    block_partials<kBlock>(acc, partials);
+}
+
+// Partial dots x.py, y.px, x.px, y.py (the asymmetry measure of the appendix
+// on symmetry), summed by k_sum_partials.
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dot4(size_t n, const T* __restrict__ x, const T* __restrict__ y,
+                                                 const T* __restrict__ px, const T* __restrict__ py, double* partials) {
+    double acc[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
+        const double xi = (double)x[i], yi = (double)y[i], pxi = (double)px[i], pyi = (double)py[i];
+        acc[0] += xi * pyi;
+        acc[1] += yi * pxi;
+        acc[2] += xi * pxi;
+        acc[3] += yi * pyi;
+    }
+    block_partials<kBlock>(acc, partials);
+}
+
+// out[w] = sum of the nparts partials of value w (block order), w < kRedWidth.
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials, int nparts,
+                                                         double* __restrict__ out) {
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nparts; b += kBlock)
+#pragma unroll
+        for (int w = 0; w < kRedWidth; ++w) v[w] += partials[(size_t)w * kMaxRedBlocks + b];
+    __shared__ double sh[kRedWidth][kBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int w = 0; w < kRedWidth; ++w) v[w] = wave_sum(v[w]);
+    if (lane == 0)
+#pragma unroll
+        for (int w = 0; w < kRedWidth; ++w) sh[w][wid] = v[w];
+    __syncthreads();
+    if (threadIdx.x < kRedWidth) {
+        double t = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i) t += sh[threadIdx.x][i];
+        out[threadIdx.x] = t;
+    }
 }
 
 // x_out = x (the current solution buffer) on fluid cells, 0 elsewhere, in double.

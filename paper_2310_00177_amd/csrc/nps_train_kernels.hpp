@@ -71,19 +71,21 @@ __device__ __forceinline__ void write_wgrad_partial(const T (&acc)[(kWGrad + kBl
 
 // Backward of one up block at level l:  x = c1 x1 + c2 CConv_2(Interp(xc)).
 // Given gx = dL/dx: writes gx1 = c1 gx (the x1 share), gr2 = CConv_2^T(c2 gx),
-// and a partial of the CConv_2 parameter sums and of dL/dc1 = gx.x1,
-// dL/dc2 = gx.x2.  Level 1 (L1): gx is masked to fluid first.
-template <class T, bool L1>
+// and (WGRAD) a partial of the CConv_2 parameter sums and of dL/dc1 = gx.x1,
+// dL/dc2 = gx.x2.  Level 1 (L1): gx is masked to fluid first.  Without
+// WGRAD this is the up block's part of the adjoint P^T (xc, x1, x2 and part
+// are not read).
+template <class T, bool L1, bool WGRAD>
 __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img, Grid g, const T* __restrict__ gx_in,
                                                    const T* __restrict__ xc, const T* __restrict__ x1,
                                                    const T* __restrict__ x2, const T* __restrict__ k2, const State* st,
                                                    int lvl, T* __restrict__ gx1, T* __restrict__ gr2, double* part) {
     const T c1 = (T)st->c1[lvl], c2 = (T)st->c2[lvl];
     __shared__ uint32_t img_s[kHaloP];
-    __shared__ T r_s[kHaloP];       // Interp(xc): the block's input
+    __shared__ T r_s[WGRAD ? kHaloP : 1];       // Interp(xc): the block's input
     __shared__ T g_s[kHaloP];       // gx (masked at level 1); the block's output gradient is c2 gx
-    __shared__ T c_s[kCoarseTileP];
-    __shared__ T u_s[kTaps * kUStride];
+    __shared__ T c_s[WGRAD ? kCoarseTileP : 1];
+    __shared__ T u_s[WGRAD ? kTaps * kUStride : 1];
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
     T acc[NO];
 #pragma unroll
@@ -96,7 +98,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
     for (TileSpan sp = tile_span(tl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const TileOrigin o = tile_origin(sp.t0, tl);
         __syncthreads();
-        stage_image_interp<L1, kStored, T>(img_s, nullptr, img, r_s, c_s, xc, g, o);
+        if constexpr (WGRAD) stage_image_interp<L1, kStored, T>(img_s, nullptr, img, r_s, c_s, xc, g, o);
+        else stage_image<L1>(img_s, img, g, o);
         for (int i = threadIdx.x; i < kHalo; i += kBlock) {
             const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
             const int xx = o.x0 + hx - 1, yy = o.y0 + hy - 1, zz = o.z0 + hz - 1;
@@ -114,11 +117,14 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
         const T gxp = g_s[base];
         const T gself = c2 * gxp;    // dL/dx2(p)
-        for (int t = 0; t < kTaps; ++t) u_s[t * kUStride + threadIdx.x] = active ? gself * r_s[base + halo_off(t)] : T(0);
+        if constexpr (WGRAD)
+            for (int t = 0; t < kTaps; ++t) u_s[t * kUStride + threadIdx.x] = active ? gself * r_s[base + halo_off(t)] : T(0);
         if (active) {
             gx1[idx] = c1 * gxp;
-            gc1 += (double)gxp * (double)x1[idx];
-            gc2 += (double)gxp * (double)x2[idx];
+            if constexpr (WGRAD) {
+                gc1 += (double)gxp * (double)x1[idx];
+                gc2 += (double)gxp * (double)x2[idx];
+            }
             T s = T(0);
 #pragma unroll
             for (int t = 0; t < kTaps; ++t) {
@@ -127,9 +133,12 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
             }
             gr2[idx] = s;
         }
-        __syncthreads();
-        accumulate_wgrad<T, L1>(u_s, img_s, acc);
+        if constexpr (WGRAD) {
+            __syncthreads();
+            accumulate_wgrad<T, L1>(u_s, img_s, acc);
+        }
     }
+    if constexpr (!WGRAD) return;
     // dL/dc partials: block sums
     double v[kRedWidth] = {gc1, gc2, 0.0, 0.0};
     __shared__ double sh[kRedWidth][kBlock / 64];
@@ -152,15 +161,18 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
 // Backward of one down block at level l:  x1 = CConv_1(r1).  The output
 // gradient is gx1 plus, below the coarsest level, the pool adjoint of the
 // next level's input gradient (gr_next / 8 of the parent cell).  Writes
-// gr1 = CConv_1^T(g) (unless gr1 is null) and a partial of the parameter sums.
-template <class T, bool L1>
+// gr1 = CConv_1^T(g) (unless gr1 is null; at level 1 restricted to fluid,
+// where the input was) and (WGRAD) a partial of the parameter sums.
+// Without WGRAD this is the down block's part of the adjoint P^T (r1 and
+// part are not read).
+template <class T, bool L1, bool WGRAD>
 __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ img, Grid g, const T* __restrict__ gx1,
                                                      const T* __restrict__ gr_next, const T* __restrict__ r1,
                                                      const T* __restrict__ k1, T* __restrict__ gr1, double* part) {
     __shared__ uint32_t img_s[kHaloP];
-    __shared__ T r_s[kHaloP];
+    __shared__ T r_s[WGRAD ? kHaloP : 1];
     __shared__ T g_s[kHaloP];
-    __shared__ T u_s[kTaps * kUStride];
+    __shared__ T u_s[WGRAD ? kTaps * kUStride : 1];
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
     T acc[NO];
 #pragma unroll
@@ -182,17 +194,20 @@ __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ im
                 const size_t q = cell_index(g, zz, yy, xx);
                 gv = gx1[q];
                 if (gr_next) gv += gr_next[cell_index(gc, zz >> 1, yy >> 1, xx >> 1)] * T(0.125);
-                rv = r1[q];
-                if (L1 && static_cast<const uint8_t*>(img)[q] != kFluid) rv = T(0);   // input padded with zeros
+                if constexpr (WGRAD) {
+                    rv = r1[q];
+                    if (L1 && static_cast<const uint8_t*>(img)[q] != kFluid) rv = T(0);   // input padded with zeros
+                }
             }
             g_s[i] = gv;
-            r_s[i] = rv;
+            if constexpr (WGRAD) r_s[i] = rv;
         }
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const T gself = g_s[base];
-        for (int t = 0; t < kTaps; ++t) u_s[t * kUStride + threadIdx.x] = active ? gself * r_s[base + halo_off(t)] : T(0);
+        if constexpr (WGRAD)
+            for (int t = 0; t < kTaps; ++t) u_s[t * kUStride + threadIdx.x] = active ? gself * r_s[base + halo_off(t)] : T(0);
         if (active && gr1) {
             T s = T(0);
 #pragma unroll
@@ -200,12 +215,15 @@ __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ im
                 const int qz = zz - (t / 9 - 1), qy = yy - ((t / 3) % 3 - 1), qx = xx - (t % 3 - 1);
                 if (in_grid(g, qz, qy, qx)) s = fma(k1[(size_t)t * n + cell_index(g, qz, qy, qx)], g_s[base - halo_off(t)], s);
             }
+            if (L1 && img_s[base] != (uint32_t)kFluid) s = T(0);
             gr1[cell_index(g, zz, yy, xx)] = s;
         }
-        __syncthreads();
-        accumulate_wgrad<T, L1>(u_s, img_s, acc);
+        if constexpr (WGRAD) {
+            __syncthreads();
+            accumulate_wgrad<T, L1>(u_s, img_s, acc);
+        }
     }
-    write_wgrad_partial<T>(acc, part, 0.0, 0.0);
+    if constexpr (WGRAD) write_wgrad_partial<T>(acc, part, 0.0, 0.0);
 }
 
 // Adjoint of the 2x trilinear upsampling: gc(j) = sum over fine cells f of
