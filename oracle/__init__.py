@@ -12,7 +12,9 @@ Plain, slow, obviously correct NumPy in float64:
   npsdo      -- the NPSDO iteration (Alg. 1).
   pcg        -- PCG and flexible PCG with the network (the solver variants
                 of the appendix comparing PCG variants).
-  gradient   -- the training loss of Sec. "Training" and its adjoint.
+  gradient   -- the training loss of Sec. "Training" and its adjoint; the
+                network's transpose (the symmetric variant's second half).
+  lanczos    -- Ritz-vector right-hand sides (the training-data generator).
 
 Every function states the passage it follows.  Readings of passages that are
 silent or ambiguous are collected in the design notes of the repository.
@@ -21,4 +23,4 @@ Parity status: every function is pinned by the CPU test suite against
 closed forms, library routines or brute force, except the asymmetry measure
 S (a diagnostic: parity unpinned).
 """
-from . import laplacian, network, npsdo, pcg  # noqa: F401
+from . import gradient, lanczos, laplacian, network, npsdo, pcg  # noqa: F401
