@@ -221,6 +221,36 @@ size_t nps_train_workspace_bytes(nps_dims dims, int levels, int precision);
 int nps_apply_precond_transpose(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* g_d,
                                 void* y_d, int precision, void* ws_d, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Right-hand sides from Ritz vectors (the training data of Sec. "Training":
+ * Lanczos on the system matrix, Ritz vectors, normalised random linear
+ * combinations).  FP64 throughout; n = nz*ny*nx.
+ *
+ * nps_lanczos: m Lanczos steps on A~ (the matrix of nps_solve, matrix-free)
+ *   from v0_d restricted to fluid cells, with full reorthogonalisation
+ *   (classical Gram-Schmidt, twice, on rocBLAS).  Outputs, device,
+ *   caller-owned: V_d double[m*n] (column j = v_(j+1), contiguous n values,
+ *   zero off fluid), alpha_d double[m] (diagonal of T_m), beta_d double[m]
+ *   (beta_d[j] couples v_(j+1) and v_(j+2); the last is the norm of the final
+ *   residual).  *steps_h = the steps before an invariant subspace was
+ *   reached (m if none; later columns and coefficients are zero).
+ *   Workspace: nps_lanczos_workspace_bytes.  Synchronises the stream.
+ * nps_ritz_rhs: the Ritz pairs of T_m (rocSOLVER's tridiagonal QL/QR;
+ *   theta_d double[m] ascending) and k right-hand sides
+ *   rhs_d[:, i] = V Y c_i / ||V Y c_i|| for the columns c_i of coef_d
+ *   (double[m*k], column-major: the caller draws the random coefficients).
+ *   rhs_d double[n*k], column-major.  Workspace: nps_ritz_workspace_bytes.
+ *   Synchronises the stream; NPS_EBREAKDOWN if the eigensolver fails.
+ * Both create a rocBLAS handle on first use per device and thread.
+ * ------------------------------------------------------------------------ */
+size_t nps_lanczos_workspace_bytes(nps_dims dims, int m);
+int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, const double* v0_d, double* V_d, double* alpha_d,
+                double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream);
+size_t nps_ritz_workspace_bytes(int m, int k);
+int nps_ritz_rhs(const double* V_d, nps_dims dims, int m, const double* alpha_d, const double* beta_d,
+                 const double* coef_d, int k, double* rhs_d, double* theta_d, void* ws_d, size_t ws_bytes,
+                 void* stream);
+
 /* Asymmetry of the network on x, y (appendix on symmetry):
  *   *s_h = |x.P(y) - y.P(x)| / sqrt(|x.P(x)| |y.P(y)|)   (0 if the root is 0).
  * Also leaves P(x) in px_d and P(y) in py_d.  Vectors of the precision's

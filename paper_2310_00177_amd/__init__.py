@@ -20,7 +20,7 @@ from ._lib import (NPS_FP64 as FP64, NPS_FP32 as FP32, NPS_MIXED_BF16 as MIXED_B
                    NPS_MIXED_FP16 as MIXED_FP16, NPS_NPSDO as NPSDO, NPS_PCG as PCG, NPS_FPCG as FPCG,
                    STATUS_NAMES)
 
-__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "apply_precond_transpose", "asymmetry", "NpsError", "SolveInfo", "Server",
+__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "apply_precond_transpose", "asymmetry", "lanczos", "ritz_rhs", "NpsError", "SolveInfo", "Server",
            "train_workspace", "net_forward", "net_backward", "train_loss", "Precond", "TrainLoss",
            "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "NPSDO", "PCG", "FPCG", "workspace", "vector_dtype"]
 
@@ -202,6 +202,45 @@ def asymmetry(net: Net, labels: torch.Tensor, x: torch.Tensor, y: torch.Tensor, 
     if rc != _lib.NPS_OK:
         raise NpsError(rc, "nps_asymmetry")
     return val
+
+
+def lanczos(labels: torch.Tensor, v0: torch.Tensor, m: int):
+    """V, alpha, beta, steps = lanczos(labels, v0, m): m Lanczos steps on A~ with
+    full reorthogonalisation (float64).  V has shape (m, nz, ny, nx)."""
+    _check_device(labels, v0)
+    if v0.dtype != torch.float64:
+        raise ValueError("v0 must be float64")
+    dims = _dims(labels.shape)
+    V = torch.empty((m,) + tuple(labels.shape), dtype=torch.float64, device=labels.device)
+    alpha = torch.empty(m, dtype=torch.float64, device=labels.device)
+    beta = torch.empty(m, dtype=torch.float64, device=labels.device)
+    ws = torch.empty(_lib.nps_lanczos_workspace_bytes(dims, m) + 256, dtype=torch.uint8, device=labels.device)
+    wp, wb = _ws_args(ws)
+    rc, steps = _lib.nps_lanczos(labels.data_ptr(), dims, m, v0.data_ptr(), V.data_ptr(), alpha.data_ptr(),
+                                 beta.data_ptr(), wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_lanczos")
+    return V, alpha, beta, steps
+
+
+def ritz_rhs(V: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, coef: torch.Tensor):
+    """rhs, theta = ritz_rhs(V, alpha, beta, coef): coef has shape (m, k);
+    rhs has shape (k, nz, ny, nx), unit-norm normalised Ritz combinations."""
+    m = V.shape[0]
+    if coef.shape[0] != m or coef.dtype != torch.float64:
+        raise ValueError("coef must be float64 of shape (m, k)")
+    k = coef.shape[1]
+    shape = tuple(V.shape[1:])
+    cm = coef.t().contiguous()                      # column-major (m x k)
+    rhs = torch.empty((k,) + shape, dtype=torch.float64, device=V.device)
+    theta = torch.empty(m, dtype=torch.float64, device=V.device)
+    ws = torch.empty(_lib.nps_ritz_workspace_bytes(m, k) + 256, dtype=torch.uint8, device=V.device)
+    wp, wb = _ws_args(ws)
+    rc = _lib.nps_ritz_rhs(V.data_ptr(), _dims(shape), m, alpha.data_ptr(), beta.data_ptr(), cm.data_ptr(), k,
+                           rhs.data_ptr(), theta.data_ptr(), wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_ritz_rhs")
+    return rhs, theta
 
 
 class Server:

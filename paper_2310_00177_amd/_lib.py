@@ -68,6 +68,12 @@ _lib.nps_apply_precond_transpose.restype = _int
 _lib.nps_asymmetry.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _vp, _vp, _int, _vp, _sz, ctypes.POINTER(ctypes.c_double),
                                _vp]
 _lib.nps_asymmetry.restype = _int
+_lib.nps_lanczos_workspace_bytes.argtypes, _lib.nps_lanczos_workspace_bytes.restype = [nps_dims, _int], _sz
+_lib.nps_lanczos.argtypes = [_vp, nps_dims, _int, _vp, _vp, _vp, _vp, ctypes.POINTER(_int), _vp, _sz, _vp]
+_lib.nps_lanczos.restype = _int
+_lib.nps_ritz_workspace_bytes.argtypes, _lib.nps_ritz_workspace_bytes.restype = [_int, _int], _sz
+_lib.nps_ritz_rhs.argtypes = [_vp, nps_dims, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp, _sz, _vp]
+_lib.nps_ritz_rhs.restype = _int
 _lib.nps_solve.argtypes = [_vp, _vp, nps_dims, _vp, _vp, ctypes.POINTER(nps_opts), ctypes.POINTER(nps_info),
                            _vp, _sz, _vp]
 _lib.nps_solve.restype = _int
@@ -102,7 +108,8 @@ _lib.nps_last_error.argtypes, _lib.nps_last_error.restype = [], ctypes.c_char_p
 
 EXPORTED = ["nps_param_count", "nps_net_bytes", "nps_net_create", "nps_net_destroy", "nps_net_levels",
             "nps_workspace_bytes", "nps_solve_workspace_bytes", "nps_solve", "nps_apply_laplacian",
-            "nps_apply_precond", "nps_apply_precond_transpose", "nps_asymmetry", "nps_server_create",
+            "nps_apply_precond", "nps_apply_precond_transpose", "nps_asymmetry", "nps_lanczos_workspace_bytes",
+            "nps_lanczos", "nps_ritz_workspace_bytes", "nps_ritz_rhs", "nps_server_create",
             "nps_server_destroy", "nps_server_request_bytes", "nps_server_submit", "nps_server_step",
             "nps_server_poll", "nps_train_workspace_bytes", "nps_net_forward", "nps_train_loss", "nps_net_backward",
             "nps_profile_enable", "nps_profile_read", "nps_last_error"]
@@ -153,6 +160,27 @@ def nps_asymmetry(net: int, labels_d: int, dims: nps_dims, x_d: int, y_d: int, p
     rc = _lib.nps_asymmetry(net, labels_d, dims, x_d, y_d, px_d, py_d, precision, ws_d, ws_bytes,
                             ctypes.byref(out), stream)
     return rc, out.value
+
+
+def nps_lanczos_workspace_bytes(dims: nps_dims, m: int) -> int:
+    return _lib.nps_lanczos_workspace_bytes(dims, m)
+
+
+def nps_ritz_workspace_bytes(m: int, k: int) -> int:
+    return _lib.nps_ritz_workspace_bytes(m, k)
+
+
+def nps_lanczos(labels_d: int, dims: nps_dims, m: int, v0_d: int, V_d: int, alpha_d: int, beta_d: int, ws_d: int,
+                ws_bytes: int, stream: int) -> tuple:
+    """Returns (status, steps)."""
+    steps = _int()
+    rc = _lib.nps_lanczos(labels_d, dims, m, v0_d, V_d, alpha_d, beta_d, ctypes.byref(steps), ws_d, ws_bytes, stream)
+    return rc, steps.value
+
+
+def nps_ritz_rhs(V_d: int, dims: nps_dims, m: int, alpha_d: int, beta_d: int, coef_d: int, k: int, rhs_d: int,
+                 theta_d: int, ws_d: int, ws_bytes: int, stream: int) -> int:
+    return _lib.nps_ritz_rhs(V_d, dims, m, alpha_d, beta_d, coef_d, k, rhs_d, theta_d, ws_d, ws_bytes, stream)
 
 
 def nps_solve(net: int, labels_d: int, dims: nps_dims, b_d: int, x_d: int, opts: nps_opts,

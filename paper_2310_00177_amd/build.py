@@ -3,7 +3,9 @@
     python -m paper_2310_00177_amd.build        # or build() from Python
 
 Every HIP source is compiled into one translation unit (nps_api.hip includes
-the kernels) with packed-FP32 instructions disabled.
+the kernels) with packed-FP32 instructions disabled.  The right-hand-side
+generator links rocBLAS (Gram-Schmidt products, the Ritz combination GEMMs)
+and rocSOLVER (the tridiagonal eigenproblem).
 """
 from __future__ import annotations
 
@@ -38,7 +40,8 @@ def build(verbose: bool = False) -> str:
     """Compile libnps.so; returns its path.  Raises on a compile error."""
     srcs = [os.path.join(CSRC, "nps_api.hip")]
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, "-I", os.path.join(ROOT, "include"), "-I", CSRC, *srcs, "-o", tmp,
+           "-L/opt/rocm/lib", "-lrocsolver", "-lrocblas"]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)

@@ -11,6 +11,10 @@
 #include "nps_internal.hpp"
 #include "nps_kernels.hpp"
 #include "nps_train_kernels.hpp"
+#include "nps_lanczos_kernels.hpp"
+
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -1624,6 +1628,186 @@ int nps_asymmetry(const nps_net* net, const uint8_t* labels_d, nps_dims dims, co
     NPS_HIP(hipStreamSynchronize(s));
     const double den = std::sqrt(std::fabs(v[2]) * std::fabs(v[3]));
     *s_h = den > 0.0 ? std::fabs(v[0] - v[1]) / den : 0.0;
+    return NPS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Ritz-vector right-hand sides (training data of Sec. "Training")
+// ---------------------------------------------------------------------------
+namespace {
+
+// One rocBLAS handle per device and host thread, created at first use.
+rocblas_handle blas_handle() {
+    thread_local rocblas_handle h[64] = {};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    if (!h[dev] && rocblas_create_handle(&h[dev]) != rocblas_status_success) h[dev] = nullptr;
+    return h[dev];
+}
+
+struct LanczosLayout {
+    size_t w, h, partials, total;
+};
+
+LanczosLayout lanczos_layout(size_t n, int m) {
+    LanczosLayout L{};
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.w = put(sizeof(double) * n);
+    L.h = put(sizeof(double) * (size_t)m);
+    L.partials = put(sizeof(double) * kRedWidth * kMaxRedBlocks);
+    L.total = off;
+    return L;
+}
+
+struct RitzLayout {
+    size_t d, e, y, z, info, total;
+};
+
+RitzLayout ritz_layout(int m, int k) {
+    RitzLayout L{};
+    size_t off = 0;
+    auto put = [&](size_t bytes) {
+        const size_t at = off;
+        off += align256(bytes);
+        return at;
+    };
+    L.d = put(sizeof(double) * (size_t)m);
+    L.e = put(sizeof(double) * (size_t)m);
+    L.y = put(sizeof(double) * (size_t)m * m);
+    L.z = put(sizeof(double) * (size_t)m * k);
+    L.info = put(sizeof(int));
+    L.total = off;
+    return L;
+}
+
+#define NPS_BLAS(call)                                                                             \
+    do {                                                                                           \
+        const rocblas_status st_ = (call);                                                         \
+        if (st_ != rocblas_status_success)                                                         \
+            return fail(NPS_EDEVICE, "%s failed: %s", #call, rocblas_status_to_string(st_));       \
+    } while (0)
+
+}  // namespace
+
+size_t nps_lanczos_workspace_bytes(nps_dims dims, int m) {
+    if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0 || m < 1) return 0;
+    return lanczos_layout((size_t)dims.nz * dims.ny * dims.nx, m).total;
+}
+
+int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, const double* v0_d, double* V_d, double* alpha_d,
+                double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!labels_d || !v0_d || !V_d || !alpha_d || !beta_d || !steps_h || !ws_d) return fail(NPS_EINVAL, "null argument");
+    if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    const size_t n = (size_t)dims.nz * dims.ny * dims.nx;
+    if (m < 1 || n > (size_t)INT32_MAX) return fail(NPS_EINVAL, "need m >= 1 and fewer than 2^31 cells");
+    const LanczosLayout L = lanczos_layout(n, m);
+    if (ws_bytes < L.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rocblas_handle hb = blas_handle();
+    if (!hb) return fail(NPS_EDEVICE, "rocblas_create_handle failed");
+    NPS_BLAS(rocblas_set_stream(hb, s));
+    NPS_BLAS(rocblas_set_pointer_mode(hb, rocblas_pointer_mode_host));
+    const Grid g{dims.nz, dims.ny, dims.nx};
+    double* w = mptr<double>(ws_d, L.w);
+    double* h = mptr<double>(ws_d, L.h);
+    double* partials = mptr<double>(ws_d, L.partials);
+    const int eg = std::min<int>(kLzBlocks, (int)((n + kBlock - 1) / kBlock));
+    const int lg = std::min(tile_grid(g), 65536);
+    const int ni = (int)n;
+    const double one = 1.0, zero = 0.0, minus_one = -1.0;
+    auto col = [&](int j) { return V_d + (size_t)j * n; };
+    // v_1 = v0 restricted to fluid, normalised
+    NPS_TRY(launch("lanczos_vec", (double)n, s, [&] { k_lz_mask<<<eg, kBlock, 0, s>>>(n, labels_d, v0_d, w); }));
+    NPS_TRY(launch("lanczos_dot", (double)n, s, [&] { k_lz_dot<<<eg, kBlock, 0, s>>>(n, w, w, partials); }));
+    NPS_TRY(launch("lanczos_reduce", 0, s, [&] { k_lz_reduce<true><<<1, kBlock, 0, s>>>(partials, eg, h); }));
+    NPS_TRY(launch("lanczos_vec", (double)n, s, [&] { k_lz_scale<<<eg, kBlock, 0, s>>>(n, w, h, col(0)); }));
+    for (int j = 0; j < m; ++j) {
+        // w = A v_j; alpha_j = w . v_j; w -= alpha_j v_j + beta_(j-1) v_(j-1)
+        NPS_TRY(launch("lanczos_matvec", (double)n, s, [&] { k_laplacian<double><<<lg, kBlock, 0, s>>>(labels_d, g, col(j), w); }));
+        NPS_TRY(launch("lanczos_dot", (double)n, s, [&] { k_lz_dot<<<eg, kBlock, 0, s>>>(n, w, col(j), partials); }));
+        NPS_TRY(launch("lanczos_reduce", 0, s, [&] { k_lz_reduce<false><<<1, kBlock, 0, s>>>(partials, eg, alpha_d + j); }));
+        NPS_TRY(launch("lanczos_vec", (double)n, s, [&] {
+            k_lz_update<<<eg, kBlock, 0, s>>>(n, w, col(j), j > 0 ? col(j - 1) : nullptr, alpha_d + j,
+                                              j > 0 ? beta_d + j - 1 : nullptr);
+        }));
+        // full reorthogonalisation against v_1..v_(j+1), twice
+        for (int pass = 0; pass < 2; ++pass) {
+            NPS_BLAS(rocblas_dgemv(hb, rocblas_operation_transpose, ni, j + 1, &one, V_d, ni, w, 1, &zero, h, 1));
+            NPS_BLAS(rocblas_dgemv(hb, rocblas_operation_none, ni, j + 1, &minus_one, V_d, ni, h, 1, &one, w, 1));
+        }
+        // beta_j = ||w||; v_(j+1) = w / beta_j
+        NPS_TRY(launch("lanczos_dot", (double)n, s, [&] { k_lz_dot<<<eg, kBlock, 0, s>>>(n, w, w, partials); }));
+        NPS_TRY(launch("lanczos_reduce", 0, s, [&] { k_lz_reduce<true><<<1, kBlock, 0, s>>>(partials, eg, beta_d + j); }));
+        if (j + 1 < m)
+            NPS_TRY(launch("lanczos_vec", (double)n, s, [&] {
+                k_lz_next<<<eg, kBlock, 0, s>>>(n, w, beta_d + j, alpha_d, col(j + 1));
+            }));
+    }
+    // steps: the first j whose beta fell below the threshold, plus one
+    std::vector<double> a(m), b(m);
+    NPS_HIP(hipMemcpyAsync(a.data(), alpha_d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipMemcpyAsync(b.data(), beta_d, sizeof(double) * m, hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipStreamSynchronize(s));
+    const double thr = 1e-12 * std::max(std::fabs(a[0]), 1.0);
+    int steps = m;
+    for (int j = 0; j < m; ++j)
+        if (!(b[j] >= thr)) {
+            steps = j + 1;
+            break;
+        }
+    *steps_h = steps;
+    return NPS_OK;
+}
+
+size_t nps_ritz_workspace_bytes(int m, int k) {
+    if (m < 1 || k < 1) return 0;
+    return ritz_layout(m, k).total;
+}
+
+int nps_ritz_rhs(const double* V_d, nps_dims dims, int m, const double* alpha_d, const double* beta_d,
+                 const double* coef_d, int k, double* rhs_d, double* theta_d, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!V_d || !alpha_d || !beta_d || !coef_d || !rhs_d || !theta_d || !ws_d) return fail(NPS_EINVAL, "null argument");
+    if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    const size_t n = (size_t)dims.nz * dims.ny * dims.nx;
+    if (m < 1 || k < 1 || n > (size_t)INT32_MAX) return fail(NPS_EINVAL, "need m, k >= 1 and fewer than 2^31 cells");
+    const RitzLayout L = ritz_layout(m, k);
+    if (ws_bytes < L.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, L.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rocblas_handle hb = blas_handle();
+    if (!hb) return fail(NPS_EDEVICE, "rocblas_create_handle failed");
+    NPS_BLAS(rocblas_set_stream(hb, s));
+    NPS_BLAS(rocblas_set_pointer_mode(hb, rocblas_pointer_mode_host));
+    double* D = mptr<double>(ws_d, L.d);
+    double* E = mptr<double>(ws_d, L.e);
+    double* Y = mptr<double>(ws_d, L.y);
+    double* Z = mptr<double>(ws_d, L.z);
+    int* info_d = mptr<int>(ws_d, L.info);
+    // Ritz pairs of T_m (eigenvalues ascending into D, eigenvectors into Y)
+    NPS_HIP(hipMemcpyAsync(D, alpha_d, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    if (m > 1) NPS_HIP(hipMemcpyAsync(E, beta_d, sizeof(double) * (m - 1), hipMemcpyDeviceToDevice, s));
+    NPS_TRY(launch("ritz_identity", 0, s, [&] {
+        k_identity<<<std::min<int>(1024, (int)(((size_t)m * m + kBlock - 1) / kBlock)), kBlock, 0, s>>>(m, Y);
+    }));
+    NPS_BLAS(rocsolver_dsteqr(hb, rocblas_evect_tridiagonal, m, D, E, Y, m, info_d));
+    int info = 0;
+    NPS_HIP(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipMemcpyAsync(theta_d, D, sizeof(double) * m, hipMemcpyDeviceToDevice, s));
+    // Z = Y C (m x k), rhs = V Z (n x k), columns scaled to unit norm
+    const double one = 1.0, zero = 0.0;
+    NPS_BLAS(rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, m, k, m, &one, Y, m, coef_d, m, &zero, Z,
+                           m));
+    NPS_BLAS(rocblas_dgemm(hb, rocblas_operation_none, rocblas_operation_none, (int)n, k, m, &one, V_d, (int)n, Z, m,
+                           &zero, rhs_d, (int)n));
+    NPS_TRY(launch("ritz_unit_columns", (double)n * k, s, [&] { k_unit_columns<<<k, 1024, 0, s>>>(n, rhs_d); }));
+    NPS_HIP(hipStreamSynchronize(s));
+    if (info != 0) return fail(NPS_EBREAKDOWN, "tridiagonal eigensolver did not converge (%d)", info);
     return NPS_OK;
 }
 

@@ -49,3 +49,8 @@ def test_host_only_queries(repo_root):
     assert 40 * n < ws32 < 70 * n and ws64 > ws32 and wsm > ws32
     assert _lib.nps_workspace_bytes(_lib.nps_dims(128, 128, 120), 6, _lib.NPS_FP32, 2) == 0   # 120 % 32
     assert _lib.nps_workspace_bytes(d, 6, _lib.NPS_FP32, 5) == 0                              # n_ortho > 4
+
+
+def test_every_exported_symbol_has_a_python_wrapper():
+    from paper_2310_00177_amd import _lib
+    assert [n for n in _lib.EXPORTED if not callable(getattr(_lib, n, None))] == []

@@ -1,0 +1,99 @@
+"""GPU parity of the Ritz-vector right-hand-side generator (Sec. "Training")
+against the FP64 oracle, through the C ABI.
+
+The Lanczos coefficients and basis match the oracle's; a full run on a tiny
+grid gives the dense spectrum; the right-hand sides have unit norm, lie in
+the Krylov basis, and their components along the oracle's Ritz vectors are
+the given coefficients up to sign (eigenvector signs are not unique, so
+that is what two implementations share).
+"""
+import numpy as np
+import pytest
+import torch
+
+import nps_inputs as gi
+from oracle import laplacian as lap
+from oracle import lanczos as olz
+
+pytestmark = pytest.mark.gpu
+
+nps = pytest.importorskip("paper_2310_00177_amd")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("m", [1, 12, 40])
+def test_lanczos_matches_oracle(m):
+    lab = gi.gen_labels(gi.scene_c1(), seed=3)
+    v0 = np.random.default_rng(m).standard_normal(lab.shape)
+    print(f"lanczos 32^3 m={m}", flush=True)
+    V, alpha, beta, steps = nps.lanczos(dev(lab), dev(v0), m)
+    Vr, ar, br, sr = olz.lanczos(lab, v0, m)
+    assert steps == sr == m
+    scale = np.max(np.abs(ar))
+    np.testing.assert_allclose(alpha.cpu().numpy(), ar, rtol=0, atol=1e-10 * scale)
+    np.testing.assert_allclose(beta.cpu().numpy(), br, rtol=0, atol=1e-10 * scale)
+    Vg = V.cpu().numpy()
+    assert np.linalg.norm(Vg - Vr) <= 1e-8 * np.linalg.norm(Vr)
+    B = Vg.reshape(m, -1)
+    np.testing.assert_allclose(B @ B.T, np.eye(m), atol=1e-12)
+
+
+def test_full_run_gives_the_dense_spectrum():
+    lab = np.full((4, 4, 8), gi.SOLID, np.uint8)
+    lab[1:3, 1:3, 1:7] = gi.FLUID
+    lab[3, 1:3, 2:6] = gi.AIR
+    lab[1, 1, 3] = gi.SOLID
+    A, cells = lap.dense_reduced(lab)
+    v0 = np.random.default_rng(1).standard_normal(lab.shape)
+    m = len(cells) + 6
+    V, alpha, beta, steps = nps.lanczos(dev(lab), dev(v0), m)
+    assert steps == len(cells)
+    coef = torch.zeros((steps, 1), dtype=torch.float64, device="cuda")
+    coef[0, 0] = 1.0
+    _, theta = nps.ritz_rhs(V[:steps].contiguous(), alpha[:steps].contiguous(), beta[:steps].contiguous(), coef)
+    np.testing.assert_allclose(theta.cpu().numpy(), np.linalg.eigvalsh(A), rtol=1e-9, atol=1e-10)
+
+
+@pytest.mark.parametrize("shape", [None, (64, 64, 96)])
+def test_ritz_rhs_matches_oracle_up_to_signs(shape):
+    spec = gi.scene_c1() if shape is None else gi.SceneSpec(shape, 8, (3.0, 10.0), 2, ("flat", 24, 40))
+    lab = gi.gen_labels(spec, seed=5)
+    rng = np.random.default_rng(9)
+    m, k = 30, 8
+    v0 = rng.standard_normal(lab.shape)
+    coef = rng.standard_normal((m, k))
+    print(f"ritz rhs {lab.shape}", flush=True)
+    V, alpha, beta, _ = nps.lanczos(dev(lab), dev(v0), m)
+    rhs, theta = nps.ritz_rhs(V, alpha, beta, dev(coef))
+    Vr, ar, br, _ = olz.lanczos(lab, v0, m)
+    th_r, Yr = olz.ritz(ar, br)
+    np.testing.assert_allclose(theta.cpu().numpy(), th_r, rtol=1e-9, atol=1e-12)
+    R = rhs.cpu().numpy().reshape(k, -1)
+    U = Yr.T @ Vr.reshape(m, -1)                                   # oracle Ritz vectors (rows)
+    for i in range(k):
+        assert np.linalg.norm(R[i]) == pytest.approx(1.0, rel=1e-12)
+        comp = U @ R[i]
+        np.testing.assert_allclose(np.abs(comp), np.abs(coef[:, i]) / np.linalg.norm(coef[:, i]), rtol=1e-7,
+                                   atol=1e-10)
+        assert np.linalg.norm(R[i] - U.T @ comp) <= 1e-9                  # inside span(V)
+    assert np.all(rhs.cpu().numpy()[:, lab != gi.FLUID] == 0)
+
+
+def test_generated_rhs_are_solvable():
+    """A generated right-hand side is a valid system: the solver reaches 1e-6 on it.
+
+    Mixed precision (x accumulated in double): a combination of extreme Ritz
+    vectors needs more attainable accuracy than a float iterate gives.
+    """
+    lab = gi.gen_labels(gi.scene_c1(), seed=6)
+    rng = np.random.default_rng(3)
+    V, alpha, beta, _ = nps.lanczos(dev(lab), dev(rng.standard_normal(lab.shape)), 24)
+    rhs, _ = nps.ritz_rhs(V, alpha, beta, dev(rng.standard_normal((24, 2))))
+    x, info = nps.solve(nps.Net(gi.multilevel_params(6), 6), dev(lab), rhs[1].contiguous(), precision=nps.MIXED_BF16)
+    assert info.status == 0
+    assert lap.rel_residual(lab, rhs[1].cpu().numpy(), x.cpu().numpy()) < 1e-6
