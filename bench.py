@@ -68,6 +68,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true", help="skip the solver-variant comparison")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations in the CPU sample")
+    ap.add_argument("--train", action="store_true", help="training throughput (forward, loss, gradient) instead")
+    ap.add_argument("--rhs-gen", action="store_true", help="Ritz-vector right-hand-side generator instead")
+    ap.add_argument("--ritz", type=int, default=1600, help="Lanczos steps of --rhs-gen")
+    ap.add_argument("--rhs-count", type=int, default=800, help="right-hand sides of --rhs-gen")
+    ap.add_argument("--reorth", action="store_true",
+                    help="--rhs-gen with full reorthogonalisation (O(m^2 n) traffic: use a small --ritz)")
     ap.add_argument("--serving", action="store_true",
                     help="run the request-server sweep instead (Poisson arrivals, mixed grid sizes)")
     ap.add_argument("--requests", type=int, default=512)
@@ -201,10 +207,116 @@ def serving_sweep(args):
     print(json.dumps(out))
 
 
+def train_bench(args):
+    """Training throughput (Sec. "Training"): per system, y = P(b), the loss
+    ||b - A y|| and its gradient with respect to every network parameter, on
+    the 128^3 scene in FP32 (the paper trains in FP32), plus the oracle's
+    loss-and-gradient on the 32^3 scene on one host thread for context."""
+    import torch
+
+    import nps_inputs as gi
+    import paper_2310_00177_amd as nps
+
+    torch.cuda.set_device(0)
+    n = args.size
+    lab = gi.gen_labels(gi.scene_c1() if n == 32 else gi.scene_serving(n), seed=args.seed)
+    params = gi.multilevel_params(6)
+    labels = torch.from_numpy(lab).cuda()
+    rhs = [torch.from_numpy(gi.gen_rhs(lab, seed=100 + i, normalize=True)).float().cuda() for i in range(4)]
+    net = nps.Net(params, 6)
+    ws = nps.train_workspace(lab.shape, 6, nps.FP32)
+    grad = torch.zeros(gi.param_count(6), dtype=torch.float64, device="cuda")
+
+    def step(b):
+        y = nps.net_forward(net, labels, b, ws)
+        loss, gy = nps.train_loss(labels, b, y, 6, ws)
+        nps.net_backward(net, labels, b, gy, grad, ws)
+        return loss
+
+    for i in range(args.warmup):
+        step(rhs[i % 4])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        loss = step(rhs[i % 4])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    cpu = None
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import gradient as og
+        lab32 = gi.gen_labels(gi.scene_c1(), seed=1)
+        b32 = gi.gen_rhs(lab32, seed=2, normalize=True)
+        with threadpool_limits(limits=1):
+            c0 = time.perf_counter()
+            og.loss_and_grad(params, 6, lab32, b32)
+            ct = time.perf_counter() - c0
+        cpu = {"value": 1.0 / ct, "unit": "systems/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle loss + adjoint gradient of one 32^3 system on 1 thread ({ct:.2f} s); "
+                         f"the GPU line is at {n}^3 ({(n / 32) ** 3:.0f}x the cells)"}
+    out = {"metric": f"training systems/s (forward, loss, full parameter gradient) at {n}^3, FP32",
+           "value": 1.0 / dt, "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{n}^3 scene, unit-norm N(0,1) right-hand sides, L=6, {gi.param_count(6)} "
+                                  "parameters, stored kernels at every level", "loss": float(loss)},
+           "cpu_baseline": cpu}
+    print(json.dumps(out))
+
+
+def rhs_gen_bench(args):
+    """Training-data generator (Sec. "Training"): 1600 Lanczos steps with full
+    reorthogonalisation on the 128^3 system matrix, then 800 normalised
+    random combinations of the Ritz vectors (the paper's counts)."""
+    import torch
+
+    import nps_inputs as gi
+    import paper_2310_00177_amd as nps
+
+    torch.cuda.set_device(0)
+    n = args.size
+    lab = gi.gen_labels(gi.scene_c1() if n == 32 else gi.scene_serving(n), seed=args.seed)
+    m, k = args.ritz, args.rhs_count
+    rng = np.random.default_rng(5)
+    labels = torch.from_numpy(lab).cuda()
+    v0 = torch.from_numpy(rng.standard_normal(lab.shape)).cuda()
+    coef = torch.from_numpy(rng.standard_normal((m, k))).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    V, alpha, beta, steps = nps.lanczos(labels, v0, m, reorth=args.reorth)
+    t1 = time.perf_counter()
+    rhs, theta = nps.ritz_rhs(V[:steps], alpha[:steps].contiguous(), beta[:steps].contiguous(), coef[:steps])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fl = int((lab == gi.FLUID).sum())
+    print(f"# rhs-gen: lanczos {m} steps {t1 - t0:.2f} s, ritz + {k} combinations {t2 - t1:.2f} s, "
+          f"theta [{theta[0].item():.4g}, {theta[-1].item():.4g}]", file=sys.stderr, flush=True)
+    out = {"metric": f"training right-hand sides/s ({m} Ritz vectors -> {k} normalised combinations) at {n}^3",
+           "value": k / (t2 - t0), "unit": "rhs/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": (t2 - t0) * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"{n}^3 scene ({fl} fluid cells), Lanczos from N(0,1), "
+                                  f"{'full reorthogonalisation' if args.reorth else 'three-term recurrence'}, "
+                                  f"N(0,1) coefficients", "lanczos_s": t1 - t0,
+                      "ritz_s": t2 - t1, "steps": steps, "basis_GB": m * lab.size * 8 / 1e9},
+           "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
-    if args.serving and args.gpus == 1:
+    if args.gpus != 1 and (args.serving or args.train or args.rhs_gen):
+        print("bench.py measures one GPU only", file=sys.stderr)
+        sys.exit(2)
+    if args.serving:
         serving_sweep(args)
+        return
+    if args.train:
+        train_bench(args)
+        return
+    if args.rhs_gen:
+        rhs_gen_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: this solver runs a single solve per GPU and the build has "

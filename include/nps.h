@@ -227,15 +227,18 @@ int nps_apply_precond_transpose(const nps_net* net, const uint8_t* labels_d, nps
  * combinations).  FP64 throughout; n = nz*ny*nx.
  *
  * nps_lanczos: m Lanczos steps on A~ (the matrix of nps_solve, matrix-free)
- *   from v0_d restricted to fluid cells, with full reorthogonalisation
- *   (classical Gram-Schmidt, twice, on rocBLAS).  Outputs, device,
+ *   from v0_d restricted to fluid cells; reorth = 1: full
+ *   reorthogonalisation (classical Gram-Schmidt, twice, on rocBLAS; it
+ *   re-reads the whole basis every step, O(m^2 n) traffic), reorth = 0: the
+ *   plain three-term recurrence (same Krylov space, the basis loses
+ *   orthogonality as Ritz values converge).  Outputs, device,
  *   caller-owned: V_d double[m*n] (column j = v_(j+1), contiguous n values,
  *   zero off fluid), alpha_d double[m] (diagonal of T_m), beta_d double[m]
  *   (beta_d[j] couples v_(j+1) and v_(j+2); the last is the norm of the final
  *   residual).  *steps_h = the steps before an invariant subspace was
  *   reached (m if none; later columns and coefficients are zero).
  *   Workspace: nps_lanczos_workspace_bytes.  Synchronises the stream.
- * nps_ritz_rhs: the Ritz pairs of T_m (rocSOLVER's tridiagonal QL/QR;
+ * nps_ritz_rhs: the Ritz pairs of T_m (rocSOLVER's tridiagonal divide and conquer;
  *   theta_d double[m] ascending) and k right-hand sides
  *   rhs_d[:, i] = V Y c_i / ||V Y c_i|| for the columns c_i of coef_d
  *   (double[m*k], column-major: the caller draws the random coefficients).
@@ -244,8 +247,8 @@ int nps_apply_precond_transpose(const nps_net* net, const uint8_t* labels_d, nps
  * Both create a rocBLAS handle on first use per device and thread.
  * ------------------------------------------------------------------------ */
 size_t nps_lanczos_workspace_bytes(nps_dims dims, int m);
-int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, const double* v0_d, double* V_d, double* alpha_d,
-                double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream);
+int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, int reorth, const double* v0_d, double* V_d,
+                double* alpha_d, double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream);
 size_t nps_ritz_workspace_bytes(int m, int k);
 int nps_ritz_rhs(const double* V_d, nps_dims dims, int m, const double* alpha_d, const double* beta_d,
                  const double* coef_d, int k, double* rhs_d, double* theta_d, void* ws_d, size_t ws_bytes,

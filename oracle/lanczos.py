@@ -5,7 +5,9 @@ The paper runs Lanczos iterations on the system matrix, takes Ritz vectors,
 and forms normalised random linear combinations of them.  Readings (the
 paper gives no more detail): Lanczos starts from a caller-given vector
 restricted to fluid cells and keeps the basis orthonormal by full
-reorthogonalisation (classical Gram-Schmidt, applied twice); the Ritz pairs
+reorthogonalisation (classical Gram-Schmidt, applied twice), or, where that
+is too costly (it re-reads the whole basis every step), runs the plain
+three-term recurrence; the Ritz pairs
 come from the m x m tridiagonal T_m; a right-hand side is V_m Y_m c for a
 caller-given coefficient vector c (the random numbers are inputs), scaled to
 unit 2-norm.
@@ -20,8 +22,11 @@ import scipy.linalg
 from . import laplacian
 
 
-def lanczos(labels: np.ndarray, v0: np.ndarray, m: int):
+def lanczos(labels: np.ndarray, v0: np.ndarray, m: int, reorth: bool = True):
     """m Lanczos steps on A (matrix-free) from v0 restricted to fluid.
+
+    reorth=False runs the plain three-term recurrence (the basis loses
+    orthogonality as Ritz values converge, but spans the same Krylov space).
 
     Returns (V, alpha, beta, steps): V has shape (steps, *grid) with
     orthonormal rows v_1..v_steps; alpha[j], beta[j] are T's diagonal and
@@ -40,9 +45,10 @@ def lanczos(labels: np.ndarray, v0: np.ndarray, m: int):
         w = laplacian.matvec(labels, v)
         a = float(np.sum(w * v))
         w = w - a * v - b_prev * v_prev
-        B = np.stack(V).reshape(len(V), -1)
-        for _ in range(2):                                  # full reorthogonalisation
-            w = w - (B.T @ (B @ w.ravel())).reshape(w.shape)
+        if reorth:
+            B = np.stack(V).reshape(len(V), -1)
+            for _ in range(2):                              # full reorthogonalisation
+                w = w - (B.T @ (B @ w.ravel())).reshape(w.shape)
         b = float(np.linalg.norm(w))
         alpha.append(a)
         beta.append(b)

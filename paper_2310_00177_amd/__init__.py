@@ -204,9 +204,10 @@ def asymmetry(net: Net, labels: torch.Tensor, x: torch.Tensor, y: torch.Tensor, 
     return val
 
 
-def lanczos(labels: torch.Tensor, v0: torch.Tensor, m: int):
-    """V, alpha, beta, steps = lanczos(labels, v0, m): m Lanczos steps on A~ with
-    full reorthogonalisation (float64).  V has shape (m, nz, ny, nx)."""
+def lanczos(labels: torch.Tensor, v0: torch.Tensor, m: int, reorth: bool = True):
+    """V, alpha, beta, steps = lanczos(labels, v0, m): m Lanczos steps on A~,
+    with full reorthogonalisation unless reorth is false (float64).  V has
+    shape (m, nz, ny, nx)."""
     _check_device(labels, v0)
     if v0.dtype != torch.float64:
         raise ValueError("v0 must be float64")
@@ -216,8 +217,8 @@ def lanczos(labels: torch.Tensor, v0: torch.Tensor, m: int):
     beta = torch.empty(m, dtype=torch.float64, device=labels.device)
     ws = torch.empty(_lib.nps_lanczos_workspace_bytes(dims, m) + 256, dtype=torch.uint8, device=labels.device)
     wp, wb = _ws_args(ws)
-    rc, steps = _lib.nps_lanczos(labels.data_ptr(), dims, m, v0.data_ptr(), V.data_ptr(), alpha.data_ptr(),
-                                 beta.data_ptr(), wp, wb, _stream())
+    rc, steps = _lib.nps_lanczos(labels.data_ptr(), dims, m, 1 if reorth else 0, v0.data_ptr(), V.data_ptr(),
+                                 alpha.data_ptr(), beta.data_ptr(), wp, wb, _stream())
     if rc != _lib.NPS_OK:
         raise NpsError(rc, "nps_lanczos")
     return V, alpha, beta, steps

@@ -69,7 +69,7 @@ _lib.nps_asymmetry.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _vp, _vp, _int, _vp
                                _vp]
 _lib.nps_asymmetry.restype = _int
 _lib.nps_lanczos_workspace_bytes.argtypes, _lib.nps_lanczos_workspace_bytes.restype = [nps_dims, _int], _sz
-_lib.nps_lanczos.argtypes = [_vp, nps_dims, _int, _vp, _vp, _vp, _vp, ctypes.POINTER(_int), _vp, _sz, _vp]
+_lib.nps_lanczos.argtypes = [_vp, nps_dims, _int, _int, _vp, _vp, _vp, _vp, ctypes.POINTER(_int), _vp, _sz, _vp]
 _lib.nps_lanczos.restype = _int
 _lib.nps_ritz_workspace_bytes.argtypes, _lib.nps_ritz_workspace_bytes.restype = [_int, _int], _sz
 _lib.nps_ritz_rhs.argtypes = [_vp, nps_dims, _int, _vp, _vp, _vp, _int, _vp, _vp, _vp, _sz, _vp]
@@ -170,11 +170,12 @@ def nps_ritz_workspace_bytes(m: int, k: int) -> int:
     return _lib.nps_ritz_workspace_bytes(m, k)
 
 
-def nps_lanczos(labels_d: int, dims: nps_dims, m: int, v0_d: int, V_d: int, alpha_d: int, beta_d: int, ws_d: int,
-                ws_bytes: int, stream: int) -> tuple:
+def nps_lanczos(labels_d: int, dims: nps_dims, m: int, reorth: int, v0_d: int, V_d: int, alpha_d: int, beta_d: int,
+                ws_d: int, ws_bytes: int, stream: int) -> tuple:
     """Returns (status, steps)."""
     steps = _int()
-    rc = _lib.nps_lanczos(labels_d, dims, m, v0_d, V_d, alpha_d, beta_d, ctypes.byref(steps), ws_d, ws_bytes, stream)
+    rc = _lib.nps_lanczos(labels_d, dims, m, reorth, v0_d, V_d, alpha_d, beta_d, ctypes.byref(steps), ws_d, ws_bytes,
+                          stream)
     return rc, steps.value
 
 

@@ -1699,8 +1699,8 @@ size_t nps_lanczos_workspace_bytes(nps_dims dims, int m) {
     return lanczos_layout((size_t)dims.nz * dims.ny * dims.nx, m).total;
 }
 
-int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, const double* v0_d, double* V_d, double* alpha_d,
-                double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream) {
+int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, int reorth, const double* v0_d, double* V_d,
+                double* alpha_d, double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream) {
     if (!labels_d || !v0_d || !V_d || !alpha_d || !beta_d || !steps_h || !ws_d) return fail(NPS_EINVAL, "null argument");
     if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
     const size_t n = (size_t)dims.nz * dims.ny * dims.nx;
@@ -1737,7 +1737,7 @@ int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, const double* v0_
                                               j > 0 ? beta_d + j - 1 : nullptr);
         }));
         // full reorthogonalisation against v_1..v_(j+1), twice
-        for (int pass = 0; pass < 2; ++pass) {
+        for (int pass = 0; pass < (reorth ? 2 : 0); ++pass) {
             NPS_BLAS(rocblas_dgemv(hb, rocblas_operation_transpose, ni, j + 1, &one, V_d, ni, w, 1, &zero, h, 1));
             NPS_BLAS(rocblas_dgemv(hb, rocblas_operation_none, ni, j + 1, &minus_one, V_d, ni, h, 1, &one, w, 1));
         }
@@ -1795,7 +1795,7 @@ int nps_ritz_rhs(const double* V_d, nps_dims dims, int m, const double* alpha_d,
     NPS_TRY(launch("ritz_identity", 0, s, [&] {
         k_identity<<<std::min<int>(1024, (int)(((size_t)m * m + kBlock - 1) / kBlock)), kBlock, 0, s>>>(m, Y);
     }));
-    NPS_BLAS(rocsolver_dsteqr(hb, rocblas_evect_tridiagonal, m, D, E, Y, m, info_d));
+    NPS_BLAS(rocsolver_dstedc(hb, rocblas_evect_tridiagonal, m, D, E, Y, m, info_d));
     int info = 0;
     NPS_HIP(hipMemcpyAsync(&info, info_d, sizeof(int), hipMemcpyDeviceToHost, s));
     NPS_HIP(hipMemcpyAsync(theta_d, D, sizeof(double) * m, hipMemcpyDeviceToDevice, s));

@@ -97,3 +97,14 @@ def test_generated_rhs_are_solvable():
     x, info = nps.solve(nps.Net(gi.multilevel_params(6), 6), dev(lab), rhs[1].contiguous(), precision=nps.MIXED_BF16)
     assert info.status == 0
     assert lap.rel_residual(lab, rhs[1].cpu().numpy(), x.cpu().numpy()) < 1e-6
+
+
+def test_plain_recurrence_matches_oracle():
+    lab = gi.gen_labels(gi.scene_c1(), seed=7)
+    v0 = np.random.default_rng(7).standard_normal(lab.shape)
+    m = 30
+    V, alpha, beta, steps = nps.lanczos(dev(lab), dev(v0), m, reorth=False)
+    Vr, ar, br, _ = olz.lanczos(lab, v0, m, reorth=False)
+    scale = np.max(np.abs(ar))
+    np.testing.assert_allclose(alpha.cpu().numpy(), ar, rtol=0, atol=1e-9 * scale)
+    np.testing.assert_allclose(beta.cpu().numpy(), br, rtol=0, atol=1e-9 * scale)

@@ -79,3 +79,18 @@ def test_rhs_are_normalised_ritz_combinations():
         comp = U @ r
         np.testing.assert_allclose(np.abs(comp), np.abs(coef[:, i]) / np.linalg.norm(coef[:, i]), rtol=1e-8,
                                    atol=1e-12)
+
+
+def test_plain_recurrence_agrees_while_orthogonality_holds():
+    """Without reorthogonalisation the first steps (before any Ritz value
+    converges) give the same T; the three-term relation holds at every step."""
+    lab = gi.gen_labels(gi.scene_gradcheck(), seed=5)
+    v0 = np.random.default_rng(5).standard_normal(lab.shape)
+    Vf, af, bf, _ = olz.lanczos(lab, v0, 8)
+    Vp, ap, bp, _ = olz.lanczos(lab, v0, 60, reorth=False)
+    np.testing.assert_allclose(ap[:8], af, rtol=1e-9)
+    np.testing.assert_allclose(bp[:8], bf, rtol=1e-9)
+    for j in range(1, 59):
+        av = lap.matvec(lab, Vp[j])
+        rhs = ap[j] * Vp[j] + bp[j] * Vp[j + 1] + bp[j - 1] * Vp[j - 1]
+        assert np.linalg.norm(av - rhs) <= 1e-10 * np.linalg.norm(av), j
