@@ -906,24 +906,25 @@ int run_solve(Solver& sv, double* x_out, nps_info* info) {
     NPS_TRY(validation_status(sv.hs));
     if (sv.hs->bb != 0.0) {
         NPS_TRY(sv.enqueue_setup());
-        hipEvent_t ev[2];
-        NPS_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-        NPS_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-        int rc = NPS_OK;
         const int max_iter = std::max(sv.o.max_iter, 0);
         volatile HostFlags* hf = sv.hf;
-        for (int k = 1; k <= max_iter + 1 && rc == NPS_OK; ++k) {
-            rc = sv.enqueue_body(k);
-            if (rc) break;
-            if (hipEventRecord(ev[k & 1], sv.s) != hipSuccess) rc = fail(NPS_EDEVICE, "hipEventRecord failed");
-            if (!rc && k >= 2) {   // one body behind: the GPU keeps working while the host waits
-                if (hipEventSynchronize(ev[(k - 1) & 1]) != hipSuccess) rc = fail(NPS_EDEVICE, "hipEventSynchronize failed");
-                if (hf->done) break;
+        for (int k = 1; k <= max_iter + 1; ++k) {
+            NPS_TRY(sv.enqueue_body(k));
+            if (k < 2) continue;
+            // Keep about two bodies queued: wait until body k-1 has passed its
+            // residual test (the control kernel mirrors the completed
+            // iteration count, k-2 by then, and the stop flag to pinned host
+            // memory), with no marker in the stream.  An idle stream ends the
+            // wait too (the flags have then been written for good).
+            for (long spin = 0; !hf->done && hf->iter < k - 2; ++spin) {
+                if ((spin & 255) == 255) {
+                    const hipError_t q = hipStreamQuery(sv.s);
+                    if (q == hipSuccess) break;
+                    if (q != hipErrorNotReady) return fail(NPS_EDEVICE, "stream failed: %s", hipGetErrorString(q));
+                }
             }
+            if (hf->done) break;
         }
-        (void)hipEventDestroy(ev[0]);
-        (void)hipEventDestroy(ev[1]);
-        NPS_TRY(rc);
     }
     NPS_TRY(sv.enqueue_finalize(x_out));
     NPS_HIP(hipStreamSynchronize(sv.s));

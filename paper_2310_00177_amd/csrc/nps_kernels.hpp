@@ -701,9 +701,10 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
             st->done = 1;
             st->status = st->fixed ? 0 : 1;   // NPS_OK / NPS_NOT_CONVERGED
         }
-        if (hf) {
+        if (hf) {   // host memory: made visible at system scope for the polling host
             hf->iter = iter;
             hf->done = st->done;
+            __threadfence_system();
         }
     } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
         if (st->method == 0) {
@@ -729,7 +730,10 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
         if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) {
             st->done = 1;
             st->status = -6;   // NPS_EBREAKDOWN
-            if (hf) hf->done = 1;
+            if (hf) {
+                hf->done = 1;
+                __threadfence_system();
+            }
         } else {
             // NPSDO: exact line search; PCG forms: alpha = r . s / d . A d
             st->alpha = (st->method == 0 ? rd : st->rho) / dAd;
@@ -1204,24 +1208,34 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
             __syncthreads();
         }
     }
-    // up sweep: x^L = x1^L
+    // up sweep: x^L = x1^L.  Interp(x^(l+1)) is formed once per level into the
+    // level's r slot (its down input is no longer needed), then CConv_2
+    // gathers from it.
     const T* xc = x1[a.L];
     for (int l = a.L - 1; l >= a.lb; --l) {
         const Grid g = a.g[l], gc = a.g[l + 1];
         const int nl = (int)ncells(g);
         const T c1 = (T)st->c1[l - 1], c2 = (T)st->c2[l - 1];
+        T* up = rb[l];
         for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
+            const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+            up[p] = interp_at<T>(xc, gc, z, y, x);
+        }
+        __syncthreads();
+        T out[(kBottomLds / 2 + kBottomThreads - 1) / kBottomThreads];
+        int j = 0;
+        for (int p = threadIdx.x; p < nl; p += kBottomThreads, ++j) {
             const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
             const T* __restrict__ k2 = a.k2[l];
             T acc = T(0);
 #pragma unroll
-            for (int t = 0; t < kTaps; ++t) {
-                const int qz = z + t / 9 - 1, qy = y + (t / 3) % 3 - 1, qx = x + t % 3 - 1;
-                const T rv = in_grid(g, qz, qy, qx) ? interp_at<T>(xc, gc, qz, qy, qx) : T(0);
-                acc = fma(k2[(size_t)t * nl + p], rv, acc);
-            }
-            rb[l][p] = c1 * x1[l][p] + c2 * acc;
+            for (int t = 0; t < kTaps; ++t)
+                acc = fma(k2[(size_t)t * nl + p], bottom_get(up, g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+            out[j] = c1 * x1[l][p] + c2 * acc;
         }
+        __syncthreads();   // every gather from up is done before it is overwritten
+        j = 0;
+        for (int p = threadIdx.x; p < nl; p += kBottomThreads, ++j) up[p] = out[j];
         __syncthreads();
         xc = rb[l];
     }
