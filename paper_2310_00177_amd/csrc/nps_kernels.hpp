@@ -322,12 +322,16 @@ __device__ __forceinline__ T cconv_pure(const T* r_s, int base, const CConvW<T>*
     return acc;
 }
 
-// Stored kernels: K[t][cell] formed at setup.
+// Stored kernels: K[t][cell] formed at setup.  The 27 loads are issued
+// together before the multiply-adds (one memory latency, not 27).
 template <class T>
 __device__ __forceinline__ T cconv_stored(const T* r_s, int base, const T* __restrict__ kst, size_t n, size_t idx) {
+    T kv[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) kv[t] = kst[(size_t)t * n + idx];
     T acc = T(0);
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) acc = fma(kst[(size_t)t * n + idx], r_s[base + halo_off(t)], acc);
+    for (int t = 0; t < kTaps; ++t) acc = fma(kv[t], r_s[base + halo_off(t)], acc);
     return acc;
 }
 
@@ -1189,10 +1193,13 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
         for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
             const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
             const T* __restrict__ k1 = a.k1[l];
+            T kv[kTaps];
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) kv[t] = k1[(size_t)t * nl + p];
             T acc = T(0);
 #pragma unroll
             for (int t = 0; t < kTaps; ++t)
-                acc = fma(k1[(size_t)t * nl + p], bottom_get(rb[l], g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+                acc = fma(kv[t], bottom_get(rb[l], g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
             x1[l][p] = acc;
         }
         __syncthreads();
@@ -1227,10 +1234,13 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
         for (int p = threadIdx.x; p < nl; p += kBottomThreads, ++j) {
             const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
             const T* __restrict__ k2 = a.k2[l];
+            T kv[kTaps];
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) kv[t] = k2[(size_t)t * nl + p];
             T acc = T(0);
 #pragma unroll
             for (int t = 0; t < kTaps; ++t)
-                acc = fma(k2[(size_t)t * nl + p], bottom_get(up, g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+                acc = fma(kv[t], bottom_get(up, g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
             out[j] = c1 * x1[l][p] + c2 * acc;
         }
         __syncthreads();   // every gather from up is done before it is overwritten
