@@ -85,15 +85,17 @@ def parse():
 # Algorithmic HBM bytes per cell of each kernel (compulsory traffic of the
 # method, labels-only operator reads), with s = bytes per vector element and
 # xs = bytes per solution element (8 in the mixed modes, where x is double):
-#   net_down_l1   x, d, b (8), labels -> x, r, x1, pooled r
-#                 (x + alpha d, r = b - A x, CConv_1, pool)   2 xs + (3 + 1/8) s + 9
+#   residual      x, d, b (8), labels -> x, r
+#                 (x + alpha d, r = b - A x)                   2 xs + 2 s + 9
+#   net_down_l1   r, labels -> x1, pooled r (CConv_1, pool)    (2 + 1/8) s + 1
 #   net_up_l1     x2 (1/8), labels, x1, n_prev Ad -> dhat      (2 + 1/8 + n_prev) s + 1
 #   ortho_matvec  dhat, n_prev d, r, labels -> d, Ad           (4 + n_prev) s + 1
 #   net_down / net_up (coarse levels): 4 B of packed counts instead of 1 B labels
 def alg_bytes_per_cell(kernel: str, s: int, xs: int = None, n_prev: int = 2) -> float | None:
     xs = s if xs is None else xs
     table = {
-        "net_down_l1": 2 * xs + 3.125 * s + 9,
+        "residual": 2 * xs + 2 * s + 9,
+        "net_down_l1": 2.125 * s + 1,
         "net_up_l1": (2.125 + n_prev) * s + 1,
         "ortho_matvec": (4 + n_prev) * s + 1,
         "net_down": 2.125 * s + 4,
@@ -106,7 +108,8 @@ def alg_bytes_per_cell(kernel: str, s: int, xs: int = None, n_prev: int = 2) -> 
 def iteration_bytes_per_fine_cell(s: int, xs: int, n_prev: int = 2) -> float:
     """All per-iteration kernels, coarse levels weighted by their 1/8^(l-1) share."""
     coarse = sum(8.0 ** -(l - 1) for l in range(2, 7))
-    return (alg_bytes_per_cell("net_down_l1", s, xs) + alg_bytes_per_cell("net_up_l1", s, xs, n_prev)
+    return (alg_bytes_per_cell("residual", s, xs) + alg_bytes_per_cell("net_down_l1", s, xs)
+            + alg_bytes_per_cell("net_up_l1", s, xs, n_prev)
             + alg_bytes_per_cell("ortho_matvec", s, xs, n_prev)
             + coarse * (alg_bytes_per_cell("net_down", s) + alg_bytes_per_cell("net_up", s)))
 

@@ -829,11 +829,15 @@ struct SolverT : Solver {
         T* adk = mptr<T>(ws, lay.adring[slot]);
         const T* x2 = nullptr;
         int np = 0;
-        int np_down = 0;
-        NPS_TRY((run_down_l1<T, X, false>(net, labels, d, plan, lay, ws, b, x0, x1b, dpend, r, s, &np_down)));
-        NPS_TRY(launch("control", 0, s, [&] {
-            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_down, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+        // x += alpha d and r = b - A x (one-cell halo), then the network on r
+        const int np_res = persist_grid(&k_residual<T, X>, g);
+        NPS_TRY(launch("residual", cells, s, [&] {
+            k_residual<T, X><<<np_res, kBlock, 0, s>>>(labels, g, b, x0, x1b, dpend, r, st, partials);
         }));
+        NPS_TRY(launch("control", 0, s, [&] {
+            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_res, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+        }));
+        NPS_TRY((run_down_l1<T, X, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr, r, s)));
         NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
         NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
         if (o.symmetric) {   // d^ = P^T P(r)/||r||, then the dots the up kernel left out

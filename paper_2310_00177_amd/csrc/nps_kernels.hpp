@@ -801,7 +801,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
     const T* __restrict__ dpend, T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
     const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
     const State* st, double* partials, const int8_t* __restrict__ wmode) {
-    if (!HOOK && st->done) return;
+    if (st->done) return;
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
     __shared__ T r_s[kHaloP];
@@ -1320,6 +1320,62 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
             adout[idx] = ad;
             v[0] += (double)dv * (double)ad;
             v[1] += (double)rv * (double)dv;
+        }
+    });
+    block_partials<kBlock>(v, partials);
+}
+
+// The start of an iteration (Alg. 1): applies the pending update
+// x += alpha d and forms the literal residual r = b - A x of the tile's cells
+// (x staged with a one-cell halo, the stencil in Acc = double), writes x to
+// the other solution buffer (state.xcur selects, so no block reads a value
+// another block already updated) and r as the network input, and the
+// partial ||r||^2.
+template <class T, class X>
+__global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__ lab, Grid g,
+                                                     const double* __restrict__ b, X* xb0, X* xb1,
+                                                     const T* __restrict__ dpend, T* __restrict__ r, const State* st,
+                                                     double* partials) {
+    if (st->done) return;
+    __shared__ uint32_t lab_s[kHaloP];
+    __shared__ X x_s[kHaloP];
+    const bool pend = st->pending;
+    const X alpha = (X)st->alpha;
+    const int cur = st->xcur;
+    const X* __restrict__ x = cur ? xb1 : xb0;
+    X* __restrict__ xnew = cur ? xb0 : xb1;
+    const Tiles tl = tiles_of(g);
+    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
+    const int base = halo_base(lx, ly, lz);
+    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    auto load = [&](int tile) {
+        const TileOrigin o = tile_origin(tile, tl);
+        return load_batch<kHalo, XDL<X, T>>([&](int i) {
+            const HaloCell c = halo_cell(g, o, i);
+            return XDL<X, T>{*at_or<X>(x, c.q, c.in, pad_zero<X>()), *at_or(dpend, c.q, c.in, pad_zero<T>()),
+                             *at_or(lab, c.q, c.in, g_pad_solid)};
+        });
+    };
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
+        const TileOrigin o = tile_origin(tile, tl);
+        __syncthreads();
+        put_batch(pre, [&](int i, XDL<X, T> e) {
+            lab_s[i] = e.l;
+            x_s[i] = pend ? e.x + alpha * (X)e.d : e.x;
+        });
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const double bv = b[idx];
+        prefetch();
+        __syncthreads();
+        if (active) {
+            double rv = 0.0;
+            if (lab_s[base] == kFluid) rv = bv - apply_A<double, X, uint32_t>(lab_s, x_s, base, HX, HX * HY);
+            xnew[idx] = x_s[base];
+            r[idx] = (T)rv;
+            const double rt = (double)(T)rv;
+            v[0] += rt * rt;
         }
     });
     block_partials<kBlock>(v, partials);
