@@ -154,9 +154,12 @@ __device__ __forceinline__ void stage_batched(Get get, Put put) {
 }
 
 // What an element outside the grid reads: zero (vectors, counts) or the
-// solid label.
-__device__ const uint64_t g_pad_zero[2] = {0, 0};
-__device__ const uint8_t g_pad_solid[8] = {kSolid, kSolid, kSolid, kSolid, kSolid, kSolid, kSolid, kSolid};
+// solid label.  Never written; not const, so that they sit in the global
+// address space like the arrays they stand in for and a select between the
+// two stays a global (not a flat) load: flat loads share the LDS counter and
+// would make every LDS wait also wait for the loads in flight.
+__device__ uint64_t g_pad_zero[2] = {0, 0};
+__device__ uint8_t g_pad_solid[8] = {kSolid, kSolid, kSolid, kSolid, kSolid, kSolid, kSolid, kSolid};
 
 template <class V>
 __device__ __forceinline__ const V* pad_zero() {
@@ -210,7 +213,9 @@ __device__ __forceinline__ void stage_image(uint32_t* img_s, const void* img, Gr
 // loads of the tile (load(tile), issued earlier) and prefetch() issues the
 // loads of the block's next tile into pre: the body calls it once it has
 // consumed pre and issued its own loads, so the next tile's memory latency
-// overlaps the current tile's compute.
+// overlaps the current tile's compute.  Everything the body reads from
+// memory for the current tile must be issued before prefetch(): vector
+// loads retire in order, so waiting for a later one waits for the prefetch.
 template <class Load, class Body>
 __device__ __forceinline__ void tile_pipeline(int ntiles, Load load, Body body) {
     const TileSpan sp = tile_span(ntiles);
@@ -284,11 +289,25 @@ __device__ __forceinline__ int choose_mode(bool active, const uint32_t* img_s, i
 // setup (k_wave_modes; the labels do not change during a solve) when given,
 // else computed here.  Wave-uniform.
 template <bool L1>
-__device__ __forceinline__ int wave_mode(const int8_t* __restrict__ tab, int tile, int lz, bool active,
+__device__ __forceinline__ int wave_mode(const int8_t* __restrict__ tab, int entry, bool active,
                                          const uint32_t* img_s, int base, uint32_t full, bool zero_if_no_fluid,
                                          bool out_only_on_fluid) {
-    if (tab) return tab[__builtin_amdgcn_readfirstlane(tile * TZ + lz)];
-    return choose_mode<L1>(active, img_s, base, full, zero_if_no_fluid, out_only_on_fluid);
+    // in a scalar register, so that what the mode selects is read by scalar loads
+    return __builtin_amdgcn_readfirstlane(
+        tab ? entry : choose_mode<L1>(active, img_s, base, full, zero_if_no_fluid, out_only_on_fluid));
+}
+
+// The table entry of the wave's mode for a tile (0 without a table).  Read
+// at the top of the tile, before the next tile's loads are issued: vector
+// loads retire in order, so a load issued after them would wait for them.
+// The tile's TZ = 4 entries are one aligned word, read with a scalar load
+// (the tile index is uniform), so the mode lands in a scalar register and
+// the pure-window weights it selects are scalar loads too.
+__device__ __forceinline__ int wave_mode_entry(const int8_t* __restrict__ tab, int tile, int lz) {
+    static_assert(TZ == 4, "one word of the mode table per tile");
+    if (!tab) return 0;
+    const uint32_t word = reinterpret_cast<const uint32_t*>(tab)[tile];
+    return __builtin_amdgcn_readfirstlane((int)(int8_t)(word >> (8 * lz)));
 }
 
 // ---------------------------------------------------------------------------
@@ -845,6 +864,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
     };
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
+        const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
         if constexpr (HOOK) {
             put_batch(pre, [&](int i, RL<T> e) {
@@ -886,7 +906,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
             r[idx] = rv;
             v[0] += (double)rv * (double)rv;
         }
-        const int mode = wave_mode<true>(wmode, tile, lz, active, img_s, base, 1u, true, false);
+        const int mode = wave_mode<true>(wmode, wm_e, active, img_s, base, 1u, true, false);
         const T out = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) x1[idx] = out;
         out_s[threadIdx.x] = active ? out : T(0);
@@ -927,6 +947,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
     };
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
+        const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
         put_batch(pre, [&](int i, CR<T> e) {
             img_s[i] = e.c;
@@ -938,7 +959,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, tile, lz, active, img_s, base, full, false, false);
+        const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, wm_e, active, img_s, base, full, false, false);
         const T out = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) x1[idx] = out;
         if (POOL) {
@@ -1016,23 +1037,66 @@ __device__ __forceinline__ void put_image_interp(const UpLoads<T>& u, uint32_t* 
 // coarse block starts two coarse cells before the tile and its coordinates
 // were clamped into the coarse grid, which is exactly the interpolation's
 // edge rule, so no further clamping is needed here.
-template <class T>
-__device__ __forceinline__ void interp_tile(T* r_s, const T* c_s, Grid g, TileOrigin o) {
-    const int bx = o.x0 / 2 - 2, by = o.y0 / 2 - 2, bz = o.z0 / 2 - 2;
-    const T a = T(0.75), b = T(0.25);
-    for (int i = threadIdx.x; i < kHalo; i += kBlock) {
+//
+// Fine cell f (along one axis) lies between coarse cells f >> 1 (weight
+// 3/4) and its neighbour on f's side (weight 1/4): the pair (f >> 1, +1)
+// for odd f, (f >> 1 - 1, f >> 1) for even f.  Tile origins are even, so
+// for each staged element the lower corner of its 2x2x2 coarse stencil in
+// the coarse block and the parities are the same on every tile: they are
+// formed once per thread (InterpSlots, one packed word per element the
+// thread stages) and the eight corners are read at fixed offsets from the
+// lower one.
+struct InterpSlots {
+    static constexpr int K = (kHalo + kBlock - 1) / kBlock;
+    uint32_t w[K];   // corner offset | odd x, y, z << 10..12 | hx << 13 | hy << 18 | hz << 21
+};
+
+__device__ __forceinline__ InterpSlots interp_slots() {
+    static_assert(kCoarseTile <= 1024 && HX <= 32 && HY <= 8 && HZ <= 8, "slot fields");
+    InterpSlots sl;
+#pragma unroll
+    for (int k = 0; k < InterpSlots::K; ++k) {
+        const int i = min((int)threadIdx.x + k * kBlock, kHalo - 1);
         const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-        const int x = o.x0 + hx - 1, y = o.y0 + hy - 1, z = o.z0 + hz - 1;
+        // fine offset from the tile origin h - 1; its coarse cell sits at
+        // ((h - 1) >> 1) + 2 in the coarse block
+        const int ox = (hx - 1) & 1, oy = (hy - 1) & 1, oz = (hz - 1) & 1;
+        const int jx = ((hx - 1) >> 1) + 2 - (1 - ox), jy = ((hy - 1) >> 1) + 2 - (1 - oy),
+                  jz = ((hz - 1) >> 1) + 2 - (1 - oz);
+        sl.w[k] = (uint32_t)((jz * CYS + jy) * CXS + jx) | (uint32_t)ox << 10 | (uint32_t)oy << 11 |
+                  (uint32_t)oz << 12 | (uint32_t)hx << 13 | (uint32_t)hy << 18 | (uint32_t)hz << 21;
+    }
+    return sl;
+}
+
+template <class T>
+__device__ __forceinline__ T interp_lerp(T lo, T hi, bool odd) {   // odd: lo is the own cell
+    return odd ? T(0.75) * lo + T(0.25) * hi : T(0.25) * lo + T(0.75) * hi;
+}
+
+template <class T>
+__device__ __forceinline__ void interp_tile(T* r_s, const T* c_s, Grid g, TileOrigin o, const InterpSlots& sl) {
+    // the whole haloed tile inside the grid: no per-element test
+    const bool inner = o.x0 >= 1 && o.y0 >= 1 && o.z0 >= 1 && o.x0 + TX < g.nx && o.y0 + TY < g.ny &&
+                       o.z0 + TZ < g.nz;
+    constexpr int DY = CXS, DZ = CXS * CYS;
+#pragma unroll
+    for (int k = 0; k < InterpSlots::K; ++k) {
+        const int i = threadIdx.x + k * kBlock;
+        if (k == InterpSlots::K - 1 && i >= kHalo) break;
+        const uint32_t w = sl.w[k];
+        bool in = true;
+        if (!inner) {
+            const int hx = (w >> 13) & 31, hy = (w >> 18) & 7, hz = (w >> 21) & 7;
+            in = in_grid(g, o.z0 + hz - 1, o.y0 + hy - 1, o.x0 + hx - 1);
+        }
         T v = T(0);
-        if (in_grid(g, z, y, x)) {
-            const int jx = (x >> 1) - bx, jy = (y >> 1) - by, jz = (z >> 1) - bz;
-            const int nx = jx + ((x & 1) ? 1 : -1), ny = jy + ((y & 1) ? 1 : -1), nz = jz + ((z & 1) ? 1 : -1);
-            auto at = [&](int zz, int yy, int xx) { return c_s[(zz * CYS + yy) * CXS + xx]; };
-            const T p00 = a * at(jz, jy, jx) + b * at(jz, jy, nx);
-            const T p01 = a * at(jz, ny, jx) + b * at(jz, ny, nx);
-            const T p10 = a * at(nz, jy, jx) + b * at(nz, jy, nx);
-            const T p11 = a * at(nz, ny, jx) + b * at(nz, ny, nx);
-            v = a * (a * p00 + b * p01) + b * (a * p10 + b * p11);
+        if (in) {
+            const T* c = c_s + (w & 1023u);
+            const bool ox = (w >> 10) & 1, oy = (w >> 11) & 1, oz = (w >> 12) & 1;
+            const T p00 = interp_lerp(c[0], c[1], ox), p01 = interp_lerp(c[DY], c[DY + 1], ox);
+            const T p10 = interp_lerp(c[DZ], c[DZ + 1], ox), p11 = interp_lerp(c[DZ + DY], c[DZ + DY + 1], ox);
+            v = interp_lerp(interp_lerp(p00, p01, oy), interp_lerp(p10, p11, oy), oz);
         }
         r_s[i] = v;
     }
@@ -1045,7 +1109,7 @@ __device__ __forceinline__ void stage_image_interp(uint32_t* img_s, uint32_t* fe
                                                    const T* __restrict__ xc, Grid g, TileOrigin o) {
     put_image_interp<L1, KM, T>(load_image_interp<L1, T>(img, xc, g, o), img_s, feat_s, c_s);
     __syncthreads();
-    interp_tile<T>(r_s, c_s, g, o);
+    interp_tile<T>(r_s, c_s, g, o, interp_slots());
 }
 
 // x = c1 x1 + c2 CConv_2(Interp(xc), I) on one level l >= 2.
@@ -1067,9 +1131,11 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
+    const InterpSlots isl = interp_slots();
     auto load = [&](int tile) { return load_image_interp<false, T>(cnt, xc, g, tile_origin(tile, tl)); };
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
+        const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
         put_image_interp<false, KM, T>(pre, img_s, feat_s, c_s);
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
@@ -1078,9 +1144,9 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
         const T x1v = x1[idx];
         prefetch();
         __syncthreads();
-        interp_tile<T>(r_s, c_s, g, o);
+        interp_tile<T>(r_s, c_s, g, o, isl);
         __syncthreads();
-        const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, tile, lz, active, img_s, base, full, false, false);
+        const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, wm_e, active, img_s, base, full, false, false);
         const T x2 = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) xout[idx] = c1 * x1v + c2 * x2;
         if (active && x2out) x2out[idx] = x2;
@@ -1113,9 +1179,11 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
     const T* adp[kMaxOrtho] = {ad0, ad1, ad2, ad3};
+    const InterpSlots isl = interp_slots();
     auto load = [&](int tile) { return load_image_interp<true, T>(lab, xc, g, tile_origin(tile, tl)); };
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
+        const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
         put_image_interp<true, KM, T>(pre, img_s, feat_s, c_s);
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
@@ -1129,9 +1197,9 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
         for (int j = 0; j < kMaxOrtho; ++j) adv[j] = (!HOOK && j < ndots ? adp[j] : x1)[idx];
         prefetch();
         __syncthreads();
-        interp_tile<T>(r_s, c_s, g, o);
+        interp_tile<T>(r_s, c_s, g, o, isl);
         __syncthreads();
-        const int mode = wave_mode<true>(wmode, tile, lz, active, img_s, base, 1u, false, true);
+        const int mode = wave_mode<true>(wmode, wm_e, active, img_s, base, 1u, false, true);
         const T x2 = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) {
             T out = T(0);
@@ -1162,55 +1230,91 @@ struct BottomArgs {
 
 constexpr int kBottomThreads = 512;
 constexpr int kBottomLds = 2 * 640;   // >= 2 * sum of the bottom levels' cells
+static_assert(kBottomMaxCells <= kBottomThreads, "one cell of each bottom level per thread");
 
 template <class T>
 __device__ __forceinline__ T bottom_get(const T* v, Grid g, int z, int y, int x) {
     return in_grid(g, z, y, x) ? v[cell_index(g, z, y, x)] : T(0);
 }
 
+// A load through a pointer that is known to address device memory: pointers
+// read from a kernel-argument array are generic, and a generic (flat) load
+// would share the LDS counter.
+template <class T>
+__device__ __forceinline__ T ld_global(const T* p) {
+    return *(const __attribute__((address_space(1))) T*)p;   // address-space cast (C-style only)
+}
+
+// One output of a stored-kernel CConv at cell p = (z, y, x) of grid g whose
+// input v sits in LDS (zero outside the grid).
+template <class T>
+__device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid g, int z, int y, int x) {
+    T acc = T(0);
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) acc = fma(kv[t], bottom_get(v, g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+    return acc;
+}
+
+// Levels lb and lb + 1 hold at most one cell per thread (lb has at most
+// kBottomThreads cells): every global load they need (r^lb and their stored
+// kernels) is issued at the start, so the sweep waits for one memory
+// latency instead of one per level.  Levels past lb + 1 (a handful of
+// cells) load their kernels where they are used.
 template <class T>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, const State* st) {
     if (st->done) return;
     __shared__ T buf[kBottomLds];
-    T* rb[kMaxLevels + 2];    // r^l, then x^l (up sweep output)
-    T* x1[kMaxLevels + 2];
-    int off = 0;
-    for (int l = a.lb; l <= a.L; ++l) {
-        const int nl = (int)ncells(a.g[l]);
-        rb[l] = buf + off;
-        off += nl;
-        x1[l] = buf + off;
-        off += nl;
+    const int lb = a.lb, p = threadIdx.x;
+    // level l's two LDS slots, r^l (then x^l, the up sweep output) and x1^l,
+    // follow those of the finer bottom levels; addressed from buf directly
+    // (a table of pointers would make them generic pointers)
+    auto slot = [&](int l) {
+        int off = 0;
+        for (int m = lb; m < l; ++m) off += 2 * (int)ncells(a.g[m]);
+        return off;
+    };
+    auto rb = [&](int l) { return buf + slot(l); };
+    auto x1 = [&](int l) { return buf + slot(l) + (int)ncells(a.g[l]); };
+    const int n0 = (int)ncells(a.g[lb]), n1 = lb < a.L ? (int)ncells(a.g[lb + 1]) : 1;
+    const int q0 = min(p, n0 - 1), q1 = min(p, n1 - 1);   // clamped: every load is in bounds
+    T r0 = ld_global(a.rin + q0);
+    T k1_0[kTaps], k2_0[kTaps], k1_1[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) k1_0[t] = ld_global(a.k1[lb] + (size_t)t * n0 + q0);
+    if (lb < a.L) {
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) k2_0[t] = ld_global(a.k2[lb] + (size_t)t * n0 + q0);
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) k1_1[t] = ld_global(a.k1[lb + 1] + (size_t)t * n1 + q1);
     }
-    {
-        const int nl = (int)ncells(a.g[a.lb]);
-        for (int i = threadIdx.x; i < nl; i += kBottomThreads) rb[a.lb][i] = a.rin[i];
-    }
+    if (p < n0) rb(lb)[p] = r0;
     __syncthreads();
-    for (int l = a.lb; l <= a.L; ++l) {       // down sweep and coarsest level
+    for (int l = lb; l <= a.L; ++l) {       // down sweep and coarsest level
         const Grid g = a.g[l];
         const int nl = (int)ncells(g);
-        for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
-            const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
-            const T* __restrict__ k1 = a.k1[l];
-            T kv[kTaps];
+        if (l <= lb + 1) {
+            if (p < nl) {
+                const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
+                x1(l)[p] = bottom_cconv(l == lb ? k1_0 : k1_1, rb(l), g, z, y, x);
+            }
+        } else {
+            for (int c = p; c < nl; c += kBottomThreads) {
+                const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
+                T kv[kTaps];
 #pragma unroll
-            for (int t = 0; t < kTaps; ++t) kv[t] = k1[(size_t)t * nl + p];
-            T acc = T(0);
-#pragma unroll
-            for (int t = 0; t < kTaps; ++t)
-                acc = fma(kv[t], bottom_get(rb[l], g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
-            x1[l][p] = acc;
+                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k1[l] + (size_t)t * nl + c);
+                x1(l)[c] = bottom_cconv(kv, rb(l), g, z, y, x);
+            }
         }
         __syncthreads();
         if (l < a.L) {
             const Grid gc = coarser(g);
             const int nc = (int)ncells(gc);
-            for (int q = threadIdx.x; q < nc; q += kBottomThreads) {
+            for (int q = p; q < nc; q += kBottomThreads) {
                 const int x = q % gc.nx, y = (q / gc.nx) % gc.ny, z = q / (gc.nx * gc.ny);
                 T s = T(0);
-                for (int k = 0; k < 8; ++k) s += x1[l][cell_index(g, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1))];
-                rb[l + 1][q] = s * T(0.125);
+                for (int k = 0; k < 8; ++k) s += x1(l)[cell_index(g, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1))];
+                rb(l + 1)[q] = s * T(0.125);
             }
             __syncthreads();
         }
@@ -1218,40 +1322,39 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
     // up sweep: x^L = x1^L.  Interp(x^(l+1)) is formed once per level into the
     // level's r slot (its down input is no longer needed), then CConv_2
     // gathers from it.
-    const T* xc = x1[a.L];
-    for (int l = a.L - 1; l >= a.lb; --l) {
+    const T* xc = x1(a.L);
+    for (int l = a.L - 1; l >= lb; --l) {
         const Grid g = a.g[l], gc = a.g[l + 1];
         const int nl = (int)ncells(g);
         const T c1 = (T)st->c1[l - 1], c2 = (T)st->c2[l - 1];
-        T* up = rb[l];
-        for (int p = threadIdx.x; p < nl; p += kBottomThreads) {
-            const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
-            up[p] = interp_at<T>(xc, gc, z, y, x);
+        T* up = rb(l);
+        for (int c = p; c < nl; c += kBottomThreads) {
+            const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
+            up[c] = interp_at<T>(xc, gc, z, y, x);
         }
         __syncthreads();
-        T out[(kBottomLds / 2 + kBottomThreads - 1) / kBottomThreads];
-        int j = 0;
-        for (int p = threadIdx.x; p < nl; p += kBottomThreads, ++j) {
+        // every level here has at most kBottomThreads cells: one output per thread
+        T out = T(0);
+        if (p < nl) {
             const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
-            const T* __restrict__ k2 = a.k2[l];
-            T kv[kTaps];
+            T acc;
+            if (l == lb) {
+                acc = bottom_cconv(k2_0, up, g, z, y, x);
+            } else {
+                T kv[kTaps];
 #pragma unroll
-            for (int t = 0; t < kTaps; ++t) kv[t] = k2[(size_t)t * nl + p];
-            T acc = T(0);
-#pragma unroll
-            for (int t = 0; t < kTaps; ++t)
-                acc = fma(kv[t], bottom_get(up, g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
-            out[j] = c1 * x1[l][p] + c2 * acc;
+                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k2[l] + (size_t)t * nl + p);
+                acc = bottom_cconv(kv, up, g, z, y, x);
+            }
+            out = c1 * x1(l)[p] + c2 * acc;
         }
         __syncthreads();   // every gather from up is done before it is overwritten
-        j = 0;
-        for (int p = threadIdx.x; p < nl; p += kBottomThreads, ++j) up[p] = out[j];
+        if (p < nl) up[p] = out;
         __syncthreads();
-        xc = rb[l];
+        xc = rb(l);
     }
     {   // x^lb (x1^L itself when the bottom holds only the coarsest level)
-        const int nl = (int)ncells(a.g[a.lb]);
-        for (int i = threadIdx.x; i < nl; i += kBottomThreads) a.xout[i] = xc[i];
+        for (int i = p; i < n0; i += kBottomThreads) a.xout[i] = xc[i];
     }
 }
 
