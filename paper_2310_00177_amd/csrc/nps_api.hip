@@ -116,6 +116,7 @@ Plan make_plan(nps_dims d, int levels, int precision, bool all_stored = false) {
 // Workspace carving, shared by nps_workspace_bytes, nps_solve and nps_apply_precond.
 struct Layout {
     size_t state, partials;
+    size_t dots;   // partials of the up kernel's dots (the next kernel writes partials while reading these)
     size_t counts[kMaxLevels + 1];
     size_t x1[kMaxLevels + 1];
     size_t rb[kMaxLevels + 1];
@@ -138,6 +139,7 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
     const size_t n = ncells(level_grid(d, 1));
     L.state = put(sizeof(State));
     L.partials = put(sizeof(double) * kRedWidth * kMaxRedBlocks);
+    L.dots = put(sizeof(double) * kRedWidth * kMaxRedBlocks);
     for (int l = 2; l <= levels; ++l) L.counts[l] = put(sizeof(uint32_t) * ncells(level_grid(d, l)));
     for (int l = 1; l <= levels; ++l) L.x1[l] = put(s * ncells(level_grid(d, l)));
     for (int l = 2; l <= levels; ++l) L.rb[l] = put(s * ncells(level_grid(d, l)));
@@ -511,9 +513,11 @@ int with_kmode(int km, F&& f) {
 
 // Alg. 2 below level 1: coarse down levels, bottom workgroup, coarse up
 // levels.  On return *x2 points at x^2, the input of level 1's up block.
+// res_partials (with res_np and hf): the iteration's Residual stage, run by
+// the bottom workgroup (the caller runs it itself when plan.lb > L).
 template <class T>
 int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& lay, void* ws, hipStream_t s,
-               const T** x2) {
+               const T** x2, const double* res_partials = nullptr, int res_np = 0, HostFlags* hf = nullptr) {
     const int L = net->levels;
     State* st = mptr<State>(ws, lay.state);
     const int last_down = std::min(plan.lb - 1, L);   // levels handled by k_down
@@ -555,6 +559,9 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         if (2 * cells > (size_t)kBottomLds) return fail(NPS_EINVAL, "bottom levels exceed the workgroup buffer");
         a.rin = cptr<T>(ws, lay.rb[plan.lb]);
         a.xout = mptr<T>(ws, lay.rb[plan.lb]);
+        a.res_partials = res_partials;
+        a.res_nparts = res_np;
+        a.hf = hf;
         NPS_TRY(launch("net_bottom", (double)cells, s, [&] { k_bottom<T><<<1, kBottomThreads, 0, s>>>(a, st); }));
     }
     auto x_of = [&](int l) -> const T* {   // x^l, the up-sweep output of level l
@@ -607,13 +614,14 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
     });
 }
 
-// Level-1 up kernel; *nparts receives its grid (the number of partials).
+// Level-1 up kernel; its partial dots go to lay.dots, *nparts receives its
+// grid (the number of partials).
 template <class T, bool HOOK>
 int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
               const T* x2, T* dhat, const T* const* ad, hipStream_t s, int* nparts) {
     const Grid g = level_grid(d, 1);
     State* st = mptr<State>(ws, lay.state);
-    double* partials = mptr<double>(ws, lay.partials);
+    double* partials = mptr<double>(ws, lay.dots);
     const T* x1 = cptr<T>(ws, lay.x1[1]);
     const CConvW<T>* w = cconv_block<T>(net, block_up(net, 1));
     const MfmaW* wm = mfma_block(net, block_up(net, 1));
@@ -804,6 +812,7 @@ struct SolverT : Solver {
         const double cells = (double)ncells(g);
         State* st = mptr<State>(ws, lay.state);
         double* partials = mptr<double>(ws, lay.partials);
+        double* pdots = mptr<double>(ws, lay.dots);
         X* x0 = mptr<X>(ws, lay.x[0]);
         X* x1b = mptr<X>(ws, lay.x[1]);
         T* r = mptr<T>(ws, lay.r[k & 1]);
@@ -834,11 +843,17 @@ struct SolverT : Solver {
         NPS_TRY(launch("residual", cells, s, [&] {
             k_residual<T, X><<<np_res, kBlock, 0, s>>>(labels, g, b, x0, x1b, dpend, r, st, partials);
         }));
-        NPS_TRY(launch("control", 0, s, [&] {
-            k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_res, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
-        }));
+        // The Residual stage (convergence test, 1/||r||, the dots the up
+        // kernel forms) is first needed by the up sweep, and the network is
+        // linear in r: the bottom workgroup runs it when there is one.
+        const bool res_in_bottom = plan.lb <= net->levels;
+        if (!res_in_bottom)
+            NPS_TRY(launch("control", 0, s, [&] {
+                k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_res, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+            }));
         NPS_TRY((run_down_l1<T, X, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr, r, s)));
-        NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
+        if (res_in_bottom) NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2, partials, np_res, hf_d));
+        else NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
         NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
         if (o.symmetric) {   // d^ = P^T P(r)/||r||, then the dots the up kernel left out
             T* dsym = mptr<T>(ws, tl.dsym);
@@ -846,15 +861,12 @@ struct SolverT : Solver {
             const size_t n = ncells(g);
             np = red_elem_grid(n);
             NPS_TRY(launch("sym_dots", cells, s, [&] {
-                k_dots<T><<<np, kBlock, 0, s>>>(n, dsym, ad[0], ad[1], ad[2], ad[3], st, partials);
+                k_dots<T><<<np, kBlock, 0, s>>>(n, dsym, ad[0], ad[1], ad[2], ad[3], st, pdots);
             }));
             dhat = dsym;
         }
-        if (o.n_ortho > 0)
-            NPS_TRY(launch("control", 0, s, [&] {
-                k_control<kStageDots><<<1, kCtlBlock, 0, s>>>(st, partials, np, sl[0], sl[1], sl[2], sl[3], 0.0, 0.0, 0.0,
-                                                               nullptr);
-            }));
+        // the Dots stage runs inside the ortho kernel (every block sums the dots)
+        const int dnp = o.n_ortho > 0 ? np : 0;
         int ogrid = 0;
         switch (o.n_ortho) {
             case 0: ogrid = persist_grid(&k_ortho<T, 0>, g); break;
@@ -866,7 +878,8 @@ struct SolverT : Solver {
         NPS_TRY(launch("ortho_matvec", cells, s, [&] {
             auto go = [&](auto no) {
                 k_ortho<T, decltype(no)::value><<<ogrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r,
-                                                                         dk, adk, st, partials);
+                                                                         dk, adk, st, pdots, dnp, sl[0], sl[1], sl[2],
+                                                                         sl[3], partials);
             };
             switch (o.n_ortho) {
                 case 0: go(std::integral_constant<int, 0>{}); break;

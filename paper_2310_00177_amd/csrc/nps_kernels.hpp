@@ -662,20 +662,25 @@ __global__ __launch_bounds__(kBlock) void k_wave_modes(const void* __restrict__ 
     }
 }
 
+// Rows of partials each stage sums.
 template <int STAGE>
-__global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* __restrict__ partials, int nparts,
-                                                       int i0, int i1, int i2, int i3, double d0, double d1,
-                                                       double d2, HostFlags* hf) {
-    if ((STAGE == kStageResidual || STAGE == kStageDots || STAGE == kStageStep) && st->done) return;
-    constexpr int W = STAGE == kStageScan ? 4 : STAGE == kStageAff ? 2 : STAGE == kStageResidual ? 1
-                    : STAGE == kStageDots ? kMaxOrtho : STAGE == kStageLoss ? 1 : 2;
-    __shared__ double sh[W][kCtlBlock / 64];
-    double v[W];
+constexpr int ctl_width() {
+    return STAGE == kStageScan ? 4 : STAGE == kStageAff ? 2 : STAGE == kStageResidual ? 1
+         : STAGE == kStageDots ? kMaxOrtho : STAGE == kStageLoss ? 1 : 2;
+}
+
+// Sum of rows w < rows (of W) of nparts per-block partials (structure of
+// arrays, block order, a fixed reduction tree for a given NT), left in v of
+// thread 0 of a block of NT threads.  Every thread must call it.
+template <int W, int NT>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int nparts, int rows, double (&v)[W]) {
+    __shared__ double sh[W][NT / 64];
 #pragma unroll
     for (int w = 0; w < W; ++w) v[w] = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kCtlBlock) {
+    for (int b = threadIdx.x; b < nparts; b += NT) {
 #pragma unroll
-        for (int w = 0; w < W; ++w) v[w] += partials[(size_t)w * kMaxRedBlocks + b];
+        for (int w = 0; w < W; ++w)
+            if (w < rows) v[w] += partials[(size_t)w * kMaxRedBlocks + b];
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -685,14 +690,44 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
         for (int w = 0; w < W; ++w) sh[w][wid] = v[w];
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    if (threadIdx.x == 0) {
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-        double s = 0.0;
+        for (int w = 0; w < W; ++w) {
+            double t = 0.0;
 #pragma unroll
-        for (int i = 0; i < kCtlBlock / 64; ++i) s += sh[w][i];
-        v[w] = s;
+            for (int i = 0; i < NT / 64; ++i) t += sh[w][i];
+            v[w] = t;
+        }
     }
+}
+
+// The Dots stage: the coefficients beta_j of the direction update from the
+// summed dots v (and, for the PCG forms, rho = r . d^), formed without
+// writing the state (sl: ring slots of d_(k-1), d_(k-2), ...).
+__device__ __forceinline__ void dots_betas(const State* st, const double* v, const int (&sl)[kMaxOrtho],
+                                           double (&beta)[kMaxOrtho], double& rho) {
+    rho = 0.0;
+    if (st->method == 0) {
+        for (int j = 0; j < kMaxOrtho; ++j) beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
+    } else {
+        // With s = P(r) = ||r|| d^ and directions kept scaled by 1/||r||,
+        // d^_k + c d^_(k-1) is parallel to s_k + beta d_(k-1) for
+        // c = beta ||r_(k-1)|| / ||r_k||: PCG c = rho_k / rho_(k-1),
+        // flexible PCG c = (rho_k - d^_k . r_(k-1)) / rho_(k-1), rho = r . d^.
+        rho = v[0];
+        const double num = st->method == 1 ? rho : rho - v[1];
+        beta[0] = st->nprev > 0 ? -num / st->rho_prev : 0.0;
+        for (int j = 1; j < kMaxOrtho; ++j) beta[j] = 0.0;
+    }
+}
+
+// The state update of one stage from its summed partials v (one thread).
+// The stopping decision is mirrored to host memory (hf) for the host loop.
+// The Dots stage may run in every block of a kernel at once (each with the
+// same sums): it reads no field it writes.
+template <int STAGE>
+__device__ __forceinline__ void control_update(State* st, const double* v, int i0, int i1, int i2, int i3, double d0,
+                                               double d1, double d2, HostFlags* hf) {
     if constexpr (STAGE == kStageScan) {            // d0 = tol
         st->bb = v[0];
         st->n_fluid = (int)v[1];
@@ -730,20 +765,11 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
             __threadfence_system();
         }
     } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
-        if (st->method == 0) {
-            const int sl[kMaxOrtho] = {i0, i1, i2, i3};
-            for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
-        } else {
-            // With s = P(r) = ||r|| d^ and directions kept scaled by 1/||r||,
-            // d^_k + c d^_(k-1) is parallel to s_k + beta d_(k-1) for
-            // c = beta ||r_(k-1)|| / ||r_k||: PCG c = rho_k / rho_(k-1),
-            // flexible PCG c = (rho_k - d^_k . r_(k-1)) / rho_(k-1), rho = r . d^.
-            const double rho = v[0];
-            const double num = st->method == 1 ? rho : rho - v[1];
-            st->rho = rho;
-            st->beta[0] = st->nprev > 0 ? -num / st->rho_prev : 0.0;
-            for (int j = 1; j < kMaxOrtho; ++j) st->beta[j] = 0.0;
-        }
+        const int sl[kMaxOrtho] = {i0, i1, i2, i3};
+        double beta[kMaxOrtho], rho;
+        dots_betas(st, v, sl, beta, rho);
+        for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
+        if (st->method != 0) st->rho = rho;
     } else if constexpr (STAGE == kStageLoss) {     // training loss: ||b - A y||^2
         st->rr = v[0];
     } else if constexpr (STAGE == kStageStep) {     // i0: ring slot of the new direction
@@ -764,6 +790,19 @@ __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* 
             st->pending = 1;
         }
     }
+}
+
+// The one-block control kernel: sums nparts per-block partials and updates
+// the state for one stage of the iteration.
+template <int STAGE>
+__global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* __restrict__ partials, int nparts,
+                                                       int i0, int i1, int i2, int i3, double d0, double d1,
+                                                       double d2, HostFlags* hf) {
+    if ((STAGE == kStageResidual || STAGE == kStageDots || STAGE == kStageStep) && st->done) return;
+    constexpr int W = ctl_width<STAGE>();
+    double v[W];
+    sum_partials<W, kCtlBlock>(partials, nparts, W, v);
+    if (threadIdx.x == 0) control_update<STAGE>(st, v, i0, i1, i2, i3, d0, d1, d2, hf);
 }
 
 // ---------------------------------------------------------------------------
@@ -1226,6 +1265,11 @@ struct BottomArgs {
     const T* k2[kMaxLevels + 1];
     const T* rin;
     T* xout;
+    // when set, the iteration's Residual stage runs here (sum of res_nparts
+    // partials of ||r||^2), before the network reads the state it decides
+    const double* res_partials;
+    int res_nparts;
+    HostFlags* hf;
 };
 
 constexpr int kBottomThreads = 512;
@@ -1261,7 +1305,7 @@ __device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid
 // latency instead of one per level.  Levels past lb + 1 (a handful of
 // cells) load their kernels where they are used.
 template <class T>
-__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, const State* st) {
+__global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, State* st) {
     if (st->done) return;
     __shared__ T buf[kBottomLds];
     const int lb = a.lb, p = threadIdx.x;
@@ -1286,6 +1330,17 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
         for (int t = 0; t < kTaps; ++t) k2_0[t] = ld_global(a.k2[lb] + (size_t)t * n0 + q0);
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) k1_1[t] = ld_global(a.k1[lb + 1] + (size_t)t * n1 + q1);
+    }
+    if (a.res_partials) {   // the Residual stage (its loads go out behind the ones above)
+        __shared__ int done_s;
+        double v[1];
+        sum_partials<1, kBottomThreads>(a.res_partials, a.res_nparts, 1, v);
+        if (p == 0) {
+            control_update<kStageResidual>(st, v, 0, 0, 0, 0, 0.0, 0.0, 0.0, a.hf);
+            done_s = st->done;
+        }
+        __syncthreads();
+        if (done_s) return;
     }
     if (p < n0) rb(lb)[p] = r0;
     __syncthreads();
@@ -1367,17 +1422,43 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, cons
 // d . A d and r . d.
 // NO: the number of previous-direction buffers passed (n_ortho); the first
 // nprev of them enter (state), the rest are loaded and not used.
+// The coefficients come from the Dots stage, which every block runs on its
+// own from the dnparts partials of the dots (the same sums in every block:
+// a fixed order); block 0 records them in the state.  dots and partials
+// must be different buffers (blocks write their partials while others may
+// still read the dots).
 template <class T, int NO>
 __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ dhat,
                                                   const T* __restrict__ p0, const T* __restrict__ p1,
                                                   const T* __restrict__ p2, const T* __restrict__ p3,
                                                   const T* __restrict__ r, T* __restrict__ dout, T* __restrict__ adout,
-                                                  const State* st, double* partials) {
+                                                  State* st, const double* __restrict__ dots, int dnparts, int sl0,
+                                                  int sl1, int sl2, int sl3, double* __restrict__ partials) {
     if (st->done) return;
     __shared__ uint32_t lab_s[kHaloP];
     __shared__ T d_s[kHaloP];
+    __shared__ double beta_s[kMaxOrtho];
     const int nprev = st->nprev;
-    const T bj[kMaxOrtho] = {(T)st->beta[0], (T)st->beta[1], (T)st->beta[2], (T)st->beta[3]};
+    T bj[kMaxOrtho] = {T(0), T(0), T(0), T(0)};
+    if (dnparts > 0) {   // the Dots stage
+        double dv[kMaxOrtho];
+        sum_partials<kMaxOrtho, kBlock>(dots, dnparts, st->ndots, dv);
+        if (threadIdx.x == 0) {
+            const int sl[kMaxOrtho] = {sl0, sl1, sl2, sl3};
+            double beta[kMaxOrtho], rho;
+            dots_betas(st, dv, sl, beta, rho);
+#pragma unroll
+            for (int j = 0; j < kMaxOrtho; ++j) beta_s[j] = beta[j];
+            if (blockIdx.x == 0) {
+#pragma unroll
+                for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
+                if (st->method != 0) st->rho = rho;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kMaxOrtho; ++j) bj[j] = (T)beta_s[j];
+    }
     const T* pp[kMaxOrtho] = {p0, p1, p2, p3};
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
