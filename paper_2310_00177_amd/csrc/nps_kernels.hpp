@@ -672,15 +672,27 @@ constexpr int ctl_width() {
 // Sum of rows w < rows (of W) of nparts per-block partials (structure of
 // arrays, block order, a fixed reduction tree for a given NT), left in v of
 // thread 0 of a block of NT threads.  Every thread must call it.
+// Each thread issues U partials per row before adding any: one memory
+// latency per U NT partials (a load-add loop would wait for every load in
+// turn).
 template <int W, int NT>
 __device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int nparts, int rows, double (&v)[W]) {
+    constexpr int U = 4;
     __shared__ double sh[W][NT / 64];
 #pragma unroll
     for (int w = 0; w < W; ++w) v[w] = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += NT) {
+    for (int b0 = 0; b0 < nparts; b0 += U * NT) {
+        double t[W][U];
 #pragma unroll
-        for (int w = 0; w < W; ++w)
-            if (w < rows) v[w] += partials[(size_t)w * kMaxRedBlocks + b];
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * NT + (int)threadIdx.x;
+#pragma unroll
+            for (int w = 0; w < W; ++w) t[w][u] = w < rows && b < nparts ? partials[(size_t)w * kMaxRedBlocks + b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int w = 0; w < W; ++w) v[w] += t[w][u];
     }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -1603,23 +1615,11 @@ __global__ __launch_bounds__(kBlock) void k_dot4(size_t n, const T* __restrict__
 // out[w] = sum of the nparts partials of value w (block order), w < kRedWidth.
 __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partials, int nparts,
                                                          double* __restrict__ out) {
-    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < nparts; b += kBlock)
+    double v[kRedWidth];
+    sum_partials<kRedWidth, kBlock>(partials, nparts, kRedWidth, v);
+    if (threadIdx.x == 0)
 #pragma unroll
-        for (int w = 0; w < kRedWidth; ++w) v[w] += partials[(size_t)w * kMaxRedBlocks + b];
-    __shared__ double sh[kRedWidth][kBlock / 64];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int w = 0; w < kRedWidth; ++w) v[w] = wave_sum(v[w]);
-    if (lane == 0)
-#pragma unroll
-        for (int w = 0; w < kRedWidth; ++w) sh[w][wid] = v[w];
-    __syncthreads();
-    if (threadIdx.x < kRedWidth) {
-        double t = 0.0;
-        for (int i = 0; i < kBlock / 64; ++i) t += sh[threadIdx.x][i];
-        out[threadIdx.x] = t;
-    }
+        for (int w = 0; w < kRedWidth; ++w) out[w] = v[w];
 }
 
 // x_out = x (the current solution buffer) on fluid cells, 0 elsewhere, in double.

@@ -30,17 +30,9 @@ __global__ __launch_bounds__(kBlock) void k_lz_dot(size_t n, const double* __res
 template <bool SQRT>
 __global__ __launch_bounds__(kBlock) void k_lz_reduce(const double* __restrict__ partials, int nparts,
                                                       double* __restrict__ out) {
-    double v = 0.0;
-    for (int b = threadIdx.x; b < nparts; b += kBlock) v += partials[b];
-    __shared__ double sh[kBlock / 64];
-    v = wave_sum(v);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < kBlock / 64; ++i) t += sh[i];
-        *out = SQRT ? sqrt(t) : t;
-    }
+    double v[1];
+    sum_partials<1, kBlock>(partials, nparts, 1, v);
+    if (threadIdx.x == 0) *out = SQRT ? sqrt(v[0]) : v[0];
 }
 
 // w -= alpha_j v_j + beta_(j-1) v_(j-1)   (beta_prev null on the first step).
