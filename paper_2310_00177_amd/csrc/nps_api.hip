@@ -841,7 +841,11 @@ struct SolverT : Solver {
         // x += alpha d and r = b - A x (one-cell halo), then the network on r
         const int np_res = persist_grid(&k_residual<T, X>, g);
         NPS_TRY(launch("residual", cells, s, [&] {
-            k_residual<T, X><<<np_res, kBlock, 0, s>>>(labels, g, b, x0, x1b, dpend, r, st, partials);
+            // body k reads the iterate from buffer (k - 1) & 1 (state.xcur, which
+            // every Residual stage flips) and writes the other
+            const bool odd = ((k - 1) & 1) != 0;
+            k_residual<T, X><<<np_res, kBlock, 0, s>>>(labels, g, b, odd ? x1b : x0, odd ? x0 : x1b, dpend, r, st,
+                                                       partials);
         }));
         // The Residual stage (convergence test, 1/||r||, the dots the up
         // kernel forms) is first needed by the up sweep, and the network is

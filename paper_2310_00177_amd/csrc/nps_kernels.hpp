@@ -216,17 +216,24 @@ __device__ __forceinline__ void stage_image(uint32_t* img_s, const void* img, Gr
 // overlaps the current tile's compute.  Everything the body reads from
 // memory for the current tile must be issued before prefetch(): vector
 // loads retire in order, so waiting for a later one waits for the prefetch.
+// The solve's stop flag (stop->done) is read alongside the first tile's
+// loads and tested once they are out (a test at the top of the kernel would
+// put its memory latency in front of them); returns false when it stopped.
 template <class Load, class Body>
-__device__ __forceinline__ void tile_pipeline(int ntiles, Load load, Body body) {
+__device__ __forceinline__ bool tile_pipeline(int ntiles, Load load, Body body, const State* stop) {
+    const int done = stop->done;
     const TileSpan sp = tile_span(ntiles);
-    if (sp.t0 >= sp.t1) return;
+    if (sp.t0 >= sp.t1) return !done;
     auto pre = load(sp.t0);
+    __asm__ volatile("" ::: "memory");   // the loads stay above the test
+    if (done) return false;
     for (int tile = sp.t0; tile < sp.t1; tile += sp.step) {
         const int next = tile + sp.step;
         body(tile, pre, [&] {
             if (next < sp.t1) pre = load(next);
         });
     }
+    return true;
 }
 
 template <bool L1>
@@ -733,6 +740,16 @@ __device__ __forceinline__ void dots_betas(const State* st, const double* v, con
     }
 }
 
+// The iteration count and stop flag, mirrored to pinned (fine-grained, not
+// L2-cached) host memory for the host loop, which only paces its enqueueing
+// by them: plain stores, no fence (a system-scope fence would write back the
+// whole L2).  The stream order, not these flags, orders the final state.
+__device__ __forceinline__ void host_flags(HostFlags* hf, int iter, int done) {
+    volatile HostFlags* h = hf;
+    h->iter = iter;
+    h->done = done;
+}
+
 // The state update of one stage from its summed partials v (one thread).
 // The stopping decision is mirrored to host memory (hf) for the host loop.
 // The Dots stage may run in every block of a kernel at once (each with the
@@ -753,7 +770,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
         const double rr = v[0];
         const int iter = st->iter + (st->pending ? 1 : 0);
         st->iter = iter;
-        st->xcur ^= 1;          // down_l1 wrote the other solution buffer
+        st->xcur ^= 1;          // the residual kernel wrote the other solution buffer
         st->pending = 0;
         st->rr = rr;
         st->scale = rr > 0.0 ? 1.0 / sqrt(rr) : 0.0;
@@ -771,11 +788,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
             st->done = 1;
             st->status = st->fixed ? 0 : 1;   // NPS_OK / NPS_NOT_CONVERGED
         }
-        if (hf) {   // host memory: made visible at system scope for the polling host
-            hf->iter = iter;
-            hf->done = st->done;
-            __threadfence_system();
-        }
+        if (hf) host_flags(hf, iter, st->done);
     } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
         const int sl[kMaxOrtho] = {i0, i1, i2, i3};
         double beta[kMaxOrtho], rho;
@@ -791,10 +804,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
         if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) {
             st->done = 1;
             st->status = -6;   // NPS_EBREAKDOWN
-            if (hf) {
-                hf->done = 1;
-                __threadfence_system();
-            }
+            if (hf) host_flags(hf, st->iter, 1);
         } else {
             // NPSDO: exact line search; PCG forms: alpha = r . s / d . A d
             st->alpha = (st->method == 0 ? rd : st->rho) / dAd;
@@ -810,10 +820,12 @@ template <int STAGE>
 __global__ __launch_bounds__(kCtlBlock) void k_control(State* st, const double* __restrict__ partials, int nparts,
                                                        int i0, int i1, int i2, int i3, double d0, double d1,
                                                        double d2, HostFlags* hf) {
-    if ((STAGE == kStageResidual || STAGE == kStageDots || STAGE == kStageStep) && st->done) return;
+    // the stop flag is read alongside the partials and tested after them
+    const int done = STAGE == kStageResidual || STAGE == kStageDots || STAGE == kStageStep ? st->done : 0;
     constexpr int W = ctl_width<STAGE>();
     double v[W];
     sum_partials<W, kCtlBlock>(partials, nparts, W, v);
+    if (done) return;
     if (threadIdx.x == 0) control_update<STAGE>(st, v, i0, i1, i2, i3, d0, d1, d2, hf);
 }
 
@@ -871,7 +883,6 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
     const T* __restrict__ dpend, T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
     const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
     const State* st, double* partials, const int8_t* __restrict__ wmode) {
-    if (st->done) return;
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
     __shared__ T r_s[kHaloP];
@@ -913,7 +924,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
             return ld;
         }
     };
-    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
+    const bool ran = tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
@@ -963,8 +974,8 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
         out_s[threadIdx.x] = active ? out : T(0);
         __syncthreads();
         pool_tile_to<T>(out_s, o, g, rnext);
-    });
-    if (!HOOK) block_partials<kBlock>(v, partials);
+    }, st);
+    if (!HOOK && ran) block_partials<kBlock>(v, partials);
 }
 
 // x1 = CConv_1(r, I) on one level l >= 2, and (POOL) r_next = Pool(x1).
@@ -979,7 +990,6 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
     const uint32_t* __restrict__ cnt, Grid g, uint32_t full, const T* __restrict__ rin, T* __restrict__ x1,
     T* __restrict__ rnext, const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
     const State* st, const int8_t* __restrict__ wmode) {
-    if (st->done) return;
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
     __shared__ T r_s[kHaloP];
@@ -1018,7 +1028,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
             __syncthreads();
             pool_tile_to<T>(out_s, o, g, rnext);
         }
-    });
+    }, st);
 }
 
 // Linear 2x upsampling weights along one axis (cell-centred, edges clamped):
@@ -1171,7 +1181,6 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
                                                const MfmaW* __restrict__ wm, const T* __restrict__ kst, int lvl,
                                                const State* st, T* __restrict__ x2out,
                                                const int8_t* __restrict__ wmode) {
-    if (st->done) return;
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
     __shared__ T r_s[kHaloP];
@@ -1201,7 +1210,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
         const T x2 = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) xout[idx] = c1 * x1v + c2 * x2;
         if (active && x2out) x2out[idx] = x2;
-    });
+    }, st);
 }
 
 // Level 1 of the up sweep: dhat = (c1 x1 + c2 CConv_2(Interp(x^2))) / ||r|| on
@@ -1215,7 +1224,6 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const T* __restrict__ kst, const State* st, double* partials, const T* __restrict__ ad0,
     const T* __restrict__ ad1, const T* __restrict__ ad2, const T* __restrict__ ad3, T* __restrict__ x2out,
     const int8_t* __restrict__ wmode) {
-    if (!HOOK && st->done) return;
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
     __shared__ T r_s[kHaloP];
@@ -1232,7 +1240,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const T* adp[kMaxOrtho] = {ad0, ad1, ad2, ad3};
     const InterpSlots isl = interp_slots();
     auto load = [&](int tile) { return load_image_interp<true, T>(lab, xc, g, tile_origin(tile, tl)); };
-    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
+    const bool ran = tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
@@ -1262,8 +1270,8 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
                 for (int j = 0; j < kMaxOrtho; ++j) v[j] += j < ndots ? (double)out * (double)adv[j] : 0.0;
             }
         }
-    });
-    if (!HOOK) block_partials<kBlock>(v, partials);
+    }, st);
+    if (!HOOK && ran) block_partials<kBlock>(v, partials);
 }
 
 // The smallest levels lb..L in one workgroup, in LDS, with stored kernels:
@@ -1288,10 +1296,7 @@ constexpr int kBottomThreads = 512;
 constexpr int kBottomLds = 2 * 640;   // >= 2 * sum of the bottom levels' cells
 static_assert(kBottomMaxCells <= kBottomThreads, "one cell of each bottom level per thread");
 
-template <class T>
-__device__ __forceinline__ T bottom_get(const T* v, Grid g, int z, int y, int x) {
-    return in_grid(g, z, y, x) ? v[cell_index(g, z, y, x)] : T(0);
-}
+
 
 // A load through a pointer that is known to address device memory: pointers
 // read from a kernel-argument array are generic, and a generic (flat) load
@@ -1303,11 +1308,20 @@ __device__ __forceinline__ T ld_global(const T* p) {
 
 // One output of a stored-kernel CConv at cell p = (z, y, x) of grid g whose
 // input v sits in LDS (zero outside the grid).
+// Every tap reads v (at the cell itself where the neighbour is outside the
+// grid) and a tap outside the grid has its weight zeroed instead: the reads
+// are unconditional, so the 27 of them go out together.
 template <class T>
 __device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid g, int z, int y, int x) {
+    const int self = (z * g.ny + y) * g.nx + x;
     T acc = T(0);
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) acc = fma(kv[t], bottom_get(v, g, z + t / 9 - 1, y + (t / 3) % 3 - 1, x + t % 3 - 1), acc);
+    for (int t = 0; t < kTaps; ++t) {
+        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+        const bool in = in_grid(g, z + dz, y + dy, x + dx);
+        const int q = in ? self + (dz * g.ny + dy) * g.nx + dx : self;
+        acc = fma(in ? kv[t] : T(0), v[q], acc);
+    }
     return acc;
 }
 
@@ -1318,7 +1332,7 @@ __device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid
 // cells) load their kernels where they are used.
 template <class T>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, State* st) {
-    if (st->done) return;
+    const int done = st->done;   // tested once the loads below are out
     __shared__ T buf[kBottomLds];
     const int lb = a.lb, p = threadIdx.x;
     // level l's two LDS slots, r^l (then x^l, the up sweep output) and x1^l,
@@ -1343,6 +1357,8 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) k1_1[t] = ld_global(a.k1[lb + 1] + (size_t)t * n1 + q1);
     }
+    __asm__ volatile("" ::: "memory");   // the loads stay above the test
+    if (done) return;
     if (a.res_partials) {   // the Residual stage (its loads go out behind the ones above)
         __shared__ int done_s;
         double v[1];
@@ -1517,29 +1533,26 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
             v[0] += (double)dv * (double)ad;
             v[1] += (double)rv * (double)dv;
         }
-    });
+    }, st);
     block_partials<kBlock>(v, partials);
 }
 
 // The start of an iteration (Alg. 1): applies the pending update
 // x += alpha d and forms the literal residual r = b - A x of the tile's cells
 // (x staged with a one-cell halo, the stencil in Acc = double), writes x to
-// the other solution buffer (state.xcur selects, so no block reads a value
-// another block already updated) and r as the network input, and the
-// partial ||r||^2.
+// the other solution buffer xnew (so no block reads a value another block
+// already updated; the buffers alternate with the iteration, and the
+// Residual stage flips state.xcur to match) and r as the network input, and
+// the partial ||r||^2.
 template <class T, class X>
 __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__ lab, Grid g,
-                                                     const double* __restrict__ b, X* xb0, X* xb1,
-                                                     const T* __restrict__ dpend, T* __restrict__ r, const State* st,
-                                                     double* partials) {
-    if (st->done) return;
+                                                     const double* __restrict__ b, const X* __restrict__ x,
+                                                     X* __restrict__ xnew, const T* __restrict__ dpend,
+                                                     T* __restrict__ r, const State* st, double* partials) {
     __shared__ uint32_t lab_s[kHaloP];
     __shared__ X x_s[kHaloP];
     const bool pend = st->pending;
     const X alpha = (X)st->alpha;
-    const int cur = st->xcur;
-    const X* __restrict__ x = cur ? xb1 : xb0;
-    X* __restrict__ xnew = cur ? xb0 : xb1;
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
@@ -1552,7 +1565,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
                              *at_or(lab, c.q, c.in, g_pad_solid)};
         });
     };
-    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
+    const bool ran = tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         __syncthreads();
         put_batch(pre, [&](int i, XDL<X, T> e) {
@@ -1573,8 +1586,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
             const double rt = (double)(T)rv;
             v[0] += rt * rt;
         }
-    });
-    block_partials<kBlock>(v, partials);
+    }, st);
+    if (ran) block_partials<kBlock>(v, partials);
 }
 
 // Partial dots v . a_j, j < the state's ndots (the up kernel's dots, for the
