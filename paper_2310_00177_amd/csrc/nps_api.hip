@@ -93,6 +93,14 @@ struct Plan {
     int km[kMaxLevels + 2];      // KMode per level
 };
 
+// LDS elements the bottom workgroup needs for levels lb..levels (two padded
+// slots per level).
+size_t bottom_footprint(nps_dims d, int lb, int levels) {
+    size_t e = 0;
+    for (int l = lb; l <= levels; ++l) e += 2 * (size_t)padded_cells(level_grid(d, l));
+    return e;
+}
+
 Plan make_plan(nps_dims d, int levels, int precision, bool all_stored = false) {
     Plan p = {};
     p.L = levels;
@@ -108,7 +116,9 @@ Plan make_plan(nps_dims d, int levels, int precision, bool all_stored = false) {
         else if (precision == NPS_FP32) p.km[l] = kMfmaBf16x3;
         else if (precision == NPS_MIXED_BF16) p.km[l] = kMfmaBf16;
         else p.km[l] = kMfmaF16;
-        if (l >= 2 && p.lb > levels && n <= (size_t)kBottomMaxCells) p.lb = l;
+        if (l >= 2 && p.lb > levels && n <= (size_t)kBottomMaxCells &&
+            bottom_footprint(d, l, levels) <= (size_t)kBottomLds)
+            p.lb = l;
     }
     return p;
 }
@@ -221,7 +231,7 @@ int tile_grid(Grid g) { return tile_blocks(tiles_of(g).count()); }
 // rounded to a multiple of kXcds; each block then walks its share of tiles.
 // Occupancy per kernel and the unit count per device are cached.
 template <class K>
-int persist_grid(K* kern, Grid g) {
+int persist_grid_n(K* kern, int items) {
     thread_local std::unordered_map<const void*, int> occ;
     thread_local int units[64] = {0};
     const void* f = reinterpret_cast<const void*>(kern);
@@ -241,7 +251,12 @@ int persist_grid(K* kern, Grid g) {
         units[dev] = cu;
     }
     const long want = (long)nb * units[dev];
-    return tile_blocks((int)std::min<long>(tiles_of(g).count(), want));
+    return tile_blocks((int)std::min<long>(items, want));
+}
+// Persistent grid of a tile kernel on grid g.
+template <class K>
+int persist_grid(K* kern, Grid g) {
+    return persist_grid_n(kern, tiles_of(g).count());
 }
 int red_elem_grid(size_t n) { return red_blocks((int)std::min<size_t>((n + kBlock - 1) / kBlock, 1u << 30)); }
 int elem_grid(size_t n) { return (int)std::min<size_t>(std::max<size_t>((n + kBlock - 1) / kBlock, 1), 65536); }
@@ -556,7 +571,8 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
             a.k2[l] = l < L ? cptr<T>(ws, lay.k2[l]) : nullptr;
             cells += ncells(a.g[l]);
         }
-        if (2 * cells > (size_t)kBottomLds) return fail(NPS_EINVAL, "bottom levels exceed the workgroup buffer");
+        if (bottom_footprint(d, plan.lb, L) > (size_t)kBottomLds)
+            return fail(NPS_EINVAL, "bottom levels exceed the workgroup buffer");
         a.rin = cptr<T>(ws, lay.rb[plan.lb]);
         a.xout = mptr<T>(ws, lay.rb[plan.lb]);
         a.res_partials = res_partials;
@@ -839,7 +855,7 @@ struct SolverT : Solver {
         const T* x2 = nullptr;
         int np = 0;
         // x += alpha d and r = b - A x (one-cell halo), then the network on r
-        const int np_res = persist_grid(&k_residual<T, X>, g);
+        const int np_res = persist_grid_n(&k_residual<T, X>, columns_of(g).count());
         NPS_TRY(launch("residual", cells, s, [&] {
             // body k reads the iterate from buffer (k - 1) & 1 (state.xcur, which
             // every Residual stage flips) and writes the other

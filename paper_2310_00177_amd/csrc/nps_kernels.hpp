@@ -1293,8 +1293,16 @@ struct BottomArgs {
 };
 
 constexpr int kBottomThreads = 512;
-constexpr int kBottomLds = 2 * 640;   // >= 2 * sum of the bottom levels' cells
+constexpr int kBottomLds = 3072;   // elements: >= 2 * sum of the bottom levels' padded cells
 static_assert(kBottomMaxCells <= kBottomThreads, "one cell of each bottom level per thread");
+
+// The bottom levels live in LDS with a one-cell zero border, so that every
+// CConv tap is a fixed offset with no bounds test.
+__host__ __device__ inline int padded_cells(Grid g) { return (g.nx + 2) * (g.ny + 2) * (g.nz + 2); }
+
+__device__ __forceinline__ int padded_index(Grid g, int z, int y, int x) {
+    return ((z + 1) * (g.ny + 2) + (y + 1)) * (g.nx + 2) + (x + 1);
+}
 
 
 
@@ -1308,21 +1316,32 @@ __device__ __forceinline__ T ld_global(const T* p) {
 
 // One output of a stored-kernel CConv at cell p = (z, y, x) of grid g whose
 // input v sits in LDS (zero outside the grid).
-// Every tap reads v (at the cell itself where the neighbour is outside the
-// grid) and a tap outside the grid has its weight zeroed instead: the reads
-// are unconditional, so the 27 of them go out together.
+// One output of a stored-kernel CConv at padded index c of grid g (input v
+// in the padded layout: its border is zero, the CConv's zero padding).
 template <class T>
-__device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid g, int z, int y, int x) {
-    const int self = (z * g.ny + y) * g.nx + x;
+__device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid g, int c) {
+    const int sy = g.nx + 2, sz = (g.ny + 2) * sy;
     T acc = T(0);
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) {
-        const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-        const bool in = in_grid(g, z + dz, y + dy, x + dx);
-        const int q = in ? self + (dz * g.ny + dy) * g.nx + dx : self;
-        acc = fma(in ? kv[t] : T(0), v[q], acc);
-    }
+    for (int t = 0; t < kTaps; ++t) acc = fma(kv[t], v[c + (t / 9 - 1) * sz + ((t / 3) % 3 - 1) * sy + (t % 3 - 1)], acc);
     return acc;
+}
+
+// Interp(xc) at fine cell (z, y, x) from the coarse grid gc in the padded
+// layout (coarse coordinates clamped: the interpolation's edge rule).
+template <class T>
+__device__ __forceinline__ T bottom_interp(const T* xc, Grid gc, int z, int y, int x) {
+    int jx, jxn, jy, jyn, jz, jzn;
+    up_axis(x, gc.nx, jx, jxn);
+    up_axis(y, gc.ny, jy, jyn);
+    up_axis(z, gc.nz, jz, jzn);
+    auto at = [&](int zz, int yy, int xx) { return xc[padded_index(gc, zz, yy, xx)]; };
+    const T a = T(0.75), b = T(0.25);
+    const T p00 = a * at(jz, jy, jx) + b * at(jz, jy, jxn);
+    const T p01 = a * at(jz, jyn, jx) + b * at(jz, jyn, jxn);
+    const T p10 = a * at(jzn, jy, jx) + b * at(jzn, jy, jxn);
+    const T p11 = a * at(jzn, jyn, jx) + b * at(jzn, jyn, jxn);
+    return a * (a * p00 + b * p01) + b * (a * p10 + b * p11);
 }
 
 // Levels lb and lb + 1 hold at most one cell per thread (lb has at most
@@ -1335,19 +1354,21 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
     const int done = st->done;   // tested once the loads below are out
     __shared__ T buf[kBottomLds];
     const int lb = a.lb, p = threadIdx.x;
-    // level l's two LDS slots, r^l (then x^l, the up sweep output) and x1^l,
-    // follow those of the finer bottom levels; addressed from buf directly
-    // (a table of pointers would make them generic pointers)
+    // level l's two padded LDS slots, r^l (then x^l, the up sweep output) and
+    // x1^l, follow those of the finer bottom levels; addressed from buf
+    // directly (a table of pointers would make them generic pointers)
     auto slot = [&](int l) {
         int off = 0;
-        for (int m = lb; m < l; ++m) off += 2 * (int)ncells(a.g[m]);
+        for (int m = lb; m < l; ++m) off += 2 * padded_cells(a.g[m]);
         return off;
     };
     auto rb = [&](int l) { return buf + slot(l); };
-    auto x1 = [&](int l) { return buf + slot(l) + (int)ncells(a.g[l]); };
+    auto x1 = [&](int l) { return buf + slot(l) + padded_cells(a.g[l]); };
     const int n0 = (int)ncells(a.g[lb]), n1 = lb < a.L ? (int)ncells(a.g[lb + 1]) : 1;
     const int q0 = min(p, n0 - 1), q1 = min(p, n1 - 1);   // clamped: every load is in bounds
     T r0 = ld_global(a.rin + q0);
+    // the combination weights of level lb (set up before the solve)
+    const T c1_0 = (T)st->c1[lb - 1], c2_0 = (T)st->c2[lb - 1];
     T k1_0[kTaps], k2_0[kTaps], k1_1[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) k1_0[t] = ld_global(a.k1[lb] + (size_t)t * n0 + q0);
@@ -1370,74 +1391,88 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
         __syncthreads();
         if (done_s) return;
     }
-    if (p < n0) rb(lb)[p] = r0;
+    // zero borders: clear the whole buffer, then fill the interiors
+    const int used = slot(a.L + 1);
+    for (int i = p; i < used; i += kBottomThreads) buf[i] = T(0);
+    __syncthreads();
+    // cell p of a level (at most one per thread) and its padded index
+    auto cell = [&](Grid g, int& z, int& y, int& x) {
+        x = p % g.nx;
+        y = (p / g.nx) % g.ny;
+        z = p / (g.nx * g.ny);
+        return padded_index(g, z, y, x);
+    };
+    {
+        int z, y, x;
+        const int c = cell(a.g[lb], z, y, x);
+        if (p < n0) rb(lb)[c] = r0;
+    }
     __syncthreads();
     for (int l = lb; l <= a.L; ++l) {       // down sweep and coarsest level
         const Grid g = a.g[l];
         const int nl = (int)ncells(g);
-        if (l <= lb + 1) {
-            if (p < nl) {
-                const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
-                x1(l)[p] = bottom_cconv(l == lb ? k1_0 : k1_1, rb(l), g, z, y, x);
-            }
-        } else {
-            for (int c = p; c < nl; c += kBottomThreads) {
-                const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
+        if (p < nl) {
+            int z, y, x;
+            const int c = cell(g, z, y, x);
+            if (l <= lb + 1) {
+                x1(l)[c] = bottom_cconv(l == lb ? k1_0 : k1_1, rb(l), g, c);
+            } else {
                 T kv[kTaps];
 #pragma unroll
-                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k1[l] + (size_t)t * nl + c);
-                x1(l)[c] = bottom_cconv(kv, rb(l), g, z, y, x);
+                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k1[l] + (size_t)t * nl + p);
+                x1(l)[c] = bottom_cconv(kv, rb(l), g, c);
             }
         }
         __syncthreads();
         if (l < a.L) {
             const Grid gc = coarser(g);
-            const int nc = (int)ncells(gc);
-            for (int q = p; q < nc; q += kBottomThreads) {
-                const int x = q % gc.nx, y = (q / gc.nx) % gc.ny, z = q / (gc.nx * gc.ny);
+            if (p < (int)ncells(gc)) {
+                int z, y, x;
+                const int c = cell(gc, z, y, x);
+                const T* f = x1(l);
                 T s = T(0);
-                for (int k = 0; k < 8; ++k) s += x1(l)[cell_index(g, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1))];
-                rb(l + 1)[q] = s * T(0.125);
+                for (int k = 0; k < 8; ++k) s += f[padded_index(g, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1))];
+                rb(l + 1)[c] = s * T(0.125);
             }
             __syncthreads();
         }
     }
     // up sweep: x^L = x1^L.  Interp(x^(l+1)) is formed once per level into the
-    // level's r slot (its down input is no longer needed), then CConv_2
-    // gathers from it.
+    // level's r slot (its down input is no longer needed; the border stays
+    // zero), then CConv_2 gathers from it.
     const T* xc = x1(a.L);
     for (int l = a.L - 1; l >= lb; --l) {
         const Grid g = a.g[l], gc = a.g[l + 1];
         const int nl = (int)ncells(g);
-        const T c1 = (T)st->c1[l - 1], c2 = (T)st->c2[l - 1];
+        const T c1 = l == lb ? c1_0 : (T)st->c1[l - 1], c2 = l == lb ? c2_0 : (T)st->c2[l - 1];
         T* up = rb(l);
-        for (int c = p; c < nl; c += kBottomThreads) {
-            const int x = c % g.nx, y = (c / g.nx) % g.ny, z = c / (g.nx * g.ny);
-            up[c] = interp_at<T>(xc, gc, z, y, x);
+        int z = 0, y = 0, x = 0, c = 0;
+        if (p < nl) {
+            c = cell(g, z, y, x);
+            up[c] = bottom_interp<T>(xc, gc, z, y, x);
         }
         __syncthreads();
-        // every level here has at most kBottomThreads cells: one output per thread
         T out = T(0);
         if (p < nl) {
-            const int x = p % g.nx, y = (p / g.nx) % g.ny, z = p / (g.nx * g.ny);
             T acc;
             if (l == lb) {
-                acc = bottom_cconv(k2_0, up, g, z, y, x);
+                acc = bottom_cconv(k2_0, up, g, c);
             } else {
                 T kv[kTaps];
 #pragma unroll
                 for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k2[l] + (size_t)t * nl + p);
-                acc = bottom_cconv(kv, up, g, z, y, x);
+                acc = bottom_cconv(kv, up, g, c);
             }
-            out = c1 * x1(l)[p] + c2 * acc;
+            out = c1 * x1(l)[c] + c2 * acc;
         }
         __syncthreads();   // every gather from up is done before it is overwritten
-        if (p < nl) up[p] = out;
+        if (p < nl) up[c] = out;
         __syncthreads();
         xc = rb(l);
     }
-    {   // x^lb (x1^L itself when the bottom holds only the coarsest level)
-        for (int i = p; i < n0; i += kBottomThreads) a.xout[i] = xc[i];
+    if (p < n0) {   // x^lb (x1^L itself when the bottom holds only the coarsest level)
+        int z, y, x;
+        a.xout[p] = xc[cell(a.g[lb], z, y, x)];
     }
 }
 
@@ -1537,57 +1572,121 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
     block_partials<kBlock>(v, partials);
 }
 
+// ---------------------------------------------------------------------------
+// plane-marching geometry of the 7-point kernels
+// ---------------------------------------------------------------------------
+// A block owns a footprint of PX x PY columns (one thread per column) and
+// marches it through kPlaneChunk z-planes.  Each plane is staged once, with
+// its x/y border, in rows of PX + 2 contiguous cells; the z neighbours of a
+// cell come from the planes staged before and after its own.  Against a
+// tile with a full 3-D halo this stages about 0.6x the elements, in rows
+// 3.7x longer.
+constexpr int PX = 64, PY = kBlock / PX;
+constexpr int PHX = PX + 2, PHY = PY + 2;
+constexpr int kPlane = PHX * PHY;
+constexpr int kPlaneP = pad_block(kPlane);
+constexpr int kPlaneChunk = 8;
+
+struct Columns {   // column footprints x z-chunks of a grid
+    int ncx, ncy, ncz;
+    __host__ __device__ int count() const { return ncx * ncy * ncz; }
+};
+
+__host__ __device__ inline Columns columns_of(Grid g) {
+    return Columns{(g.nx + PX - 1) / PX, (g.ny + PY - 1) / PY, (g.nz + kPlaneChunk - 1) / kPlaneChunk};
+}
+
 // The start of an iteration (Alg. 1): applies the pending update
-// x += alpha d and forms the literal residual r = b - A x of the tile's cells
-// (x staged with a one-cell halo, the stencil in Acc = double), writes x to
-// the other solution buffer xnew (so no block reads a value another block
-// already updated; the buffers alternate with the iteration, and the
-// Residual stage flips state.xcur to match) and r as the network input, and
-// the partial ||r||^2.
+// x += alpha d and forms the literal residual r = b - A x (the stencil in
+// double), writes x to the other solution buffer xnew (so no block reads a
+// value another block already updated; the buffers alternate with the
+// iteration, and the Residual stage flips state.xcur to match) and r as the
+// network input, and the partial ||r||^2.  Plane-marching: step s stages
+// plane s (x + alpha d and the labels, outside the grid x = 0 and solid)
+// and forms plane s - 1.
 template <class T, class X>
 __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__ lab, Grid g,
                                                      const double* __restrict__ b, const X* __restrict__ x,
                                                      X* __restrict__ xnew, const T* __restrict__ dpend,
                                                      T* __restrict__ r, const State* st, double* partials) {
-    __shared__ uint32_t lab_s[kHaloP];
-    __shared__ X x_s[kHaloP];
+    __shared__ uint32_t lab_s[2][kPlaneP];
+    __shared__ X x_s[2][kPlaneP];
+    const int done = st->done;   // tested once the first loads are out
     const bool pend = st->pending;
     const X alpha = (X)st->alpha;
-    const Tiles tl = tiles_of(g);
-    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-    const int base = halo_base(lx, ly, lz);
+    const Columns cl = columns_of(g);
+    const int lx = threadIdx.x % PX, ly = threadIdx.x / PX;
+    const int own = (ly + 1) * PHX + (lx + 1);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
-    auto load = [&](int tile) {
-        const TileOrigin o = tile_origin(tile, tl);
-        return load_batch<kHalo, XDL<X, T>>([&](int i) {
-            const HaloCell c = halo_cell(g, o, i);
-            return XDL<X, T>{*at_or<X>(x, c.q, c.in, pad_zero<X>()), *at_or(dpend, c.q, c.in, pad_zero<T>()),
-                             *at_or(lab, c.q, c.in, g_pad_solid)};
-        });
+    auto element = [&](int zz, int yy, int xx) {
+        const bool in = in_grid(g, zz, yy, xx);
+        const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
+        return XDL<X, T>{*at_or<X>(x, q, in, pad_zero<X>()), *at_or(dpend, q, in, pad_zero<T>()),
+                         *at_or(lab, q, in, g_pad_solid)};
     };
-    const bool ran = tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
-        const TileOrigin o = tile_origin(tile, tl);
-        __syncthreads();
-        put_batch(pre, [&](int i, XDL<X, T> e) {
-            lab_s[i] = e.l;
-            x_s[i] = pend ? e.x + alpha * (X)e.d : e.x;
-        });
-        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
-        const bool active = in_grid(g, zz, yy, xx);
-        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        const double bv = b[idx];
-        prefetch();
-        __syncthreads();
-        if (active) {
-            double rv = 0.0;
-            if (lab_s[base] == kFluid) rv = bv - apply_A<double, X, uint32_t>(lab_s, x_s, base, HX, HX * HY);
-            xnew[idx] = x_s[base];
-            r[idx] = (T)rv;
-            const double rt = (double)(T)rv;
-            v[0] += rt * rt;
+    auto plane = [&](int x0, int y0, int zz) {
+        return load_batch<kPlane, XDL<X, T>>([&](int i) { return element(zz, y0 + i / PHX - 1, x0 + i % PHX - 1); });
+    };
+    auto updated = [&](const XDL<X, T>& e) { return pend ? e.x + alpha * (X)e.d : e.x; };
+    bool first = true;
+    for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int w = sp.t0;
+        const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * kPlaneChunk;
+        const int z1 = min(z0 + kPlaneChunk, g.nz);
+        const int xx = x0 + lx, yy = y0 + ly;
+        const bool col = xx < g.nx && yy < g.ny;
+        const XDL<X, T> below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
+        auto pre = plane(x0, y0, z0);
+        if (first) {
+            __asm__ volatile("" ::: "memory");   // the loads stay above the test
+            if (done) return;
+            first = false;
         }
-    }, st);
-    if (ran) block_partials<kBlock>(v, partials);
+        X xm = updated(below);   // own column, plane s - 2
+        uint32_t lm = below.l;
+        double bv = 0.0;         // b of plane s - 1
+        for (int s = z0; s <= z1; ++s) {
+            const int cur = s & 1, prev = cur ^ 1;
+            __syncthreads();   // the reads of this buffer (plane s - 2) are done
+            put_batch(pre, [&](int i, XDL<X, T> e) {
+                lab_s[cur][i] = e.l;
+                x_s[cur][i] = updated(e);
+            });
+            const double bnext = b[col && s < z1 ? cell_index(g, s, yy, xx) : 0];
+            if (s < z1) pre = plane(x0, y0, s + 1);
+            __syncthreads();   // plane s is staged
+            if (s > z0) {      // the own cell of plane c = s - 1
+                const uint32_t lc = lab_s[prev][own];
+                const X xc = x_s[prev][own];
+                if (col) {
+                    double rv = 0.0;
+                    if (lc == kFluid) {   // the mixed-BC 7-point row, neighbours z-, z+, y-, y+, x-, x+
+                        const uint32_t nl[6] = {lm, lab_s[cur][own], lab_s[prev][own - PHX], lab_s[prev][own + PHX],
+                                                lab_s[prev][own - 1], lab_s[prev][own + 1]};
+                        const X nv[6] = {xm, x_s[cur][own], x_s[prev][own - PHX], x_s[prev][own + PHX],
+                                         x_s[prev][own - 1], x_s[prev][own + 1]};
+                        int cnt = 0;
+                        double sum = 0.0;
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) {
+                            cnt += (nl[k] != (uint32_t)kSolid);
+                            if (nl[k] == (uint32_t)kFluid) sum += (double)nv[k];
+                        }
+                        rv = bv - ((double)cnt * (double)xc - sum);
+                    }
+                    const size_t q = cell_index(g, s - 1, yy, xx);
+                    xnew[q] = xc;
+                    r[q] = (T)rv;
+                    const double rt = (double)(T)rv;
+                    v[0] += rt * rt;
+                }
+                xm = xc;
+                lm = lc;
+            }
+            bv = bnext;
+        }
+    }
+    if (!first || !done) block_partials<kBlock>(v, partials);
 }
 
 // Partial dots v . a_j, j < the state's ndots (the up kernel's dots, for the
