@@ -889,11 +889,11 @@ struct SolverT : Solver {
         const int dnp = o.n_ortho > 0 ? np : 0;
         int ogrid = 0;
         switch (o.n_ortho) {
-            case 0: ogrid = persist_grid(&k_ortho<T, 0>, g); break;
-            case 1: ogrid = persist_grid(&k_ortho<T, 1>, g); break;
-            case 2: ogrid = persist_grid(&k_ortho<T, 2>, g); break;
-            case 3: ogrid = persist_grid(&k_ortho<T, 3>, g); break;
-            default: ogrid = persist_grid(&k_ortho<T, 4>, g); break;
+            case 0: ogrid = persist_grid_n(&k_ortho<T, 0>, columns_of(g).count()); break;
+            case 1: ogrid = persist_grid_n(&k_ortho<T, 1>, columns_of(g).count()); break;
+            case 2: ogrid = persist_grid_n(&k_ortho<T, 2>, columns_of(g).count()); break;
+            case 3: ogrid = persist_grid_n(&k_ortho<T, 3>, columns_of(g).count()); break;
+            default: ogrid = persist_grid_n(&k_ortho<T, 4>, columns_of(g).count()); break;
         }
         NPS_TRY(launch("ortho_matvec", cells, s, [&] {
             auto go = [&](auto no) {

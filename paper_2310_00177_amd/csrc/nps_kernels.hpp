@@ -1479,6 +1479,30 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
 // ---------------------------------------------------------------------------
 // Krylov kernels (Alg. 1)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// plane-marching geometry of the 7-point kernels
+// ---------------------------------------------------------------------------
+// A block owns a footprint of PX x PY columns (one thread per column) and
+// marches it through kPlaneChunk z-planes.  Each plane is staged once, with
+// its x/y border, in rows of PX + 2 contiguous cells; the z neighbours of a
+// cell come from the planes staged before and after its own.  Against a
+// tile with a full 3-D halo this stages about 0.6x the elements, in rows
+// 3.7x longer.
+constexpr int PX = 64, PY = kBlock / PX;
+constexpr int PHX = PX + 2, PHY = PY + 2;
+constexpr int kPlane = PHX * PHY;
+constexpr int kPlaneP = pad_block(kPlane);
+constexpr int kPlaneChunk = 8;
+
+struct Columns {   // column footprints x z-chunks of a grid
+    int ncx, ncy, ncz;
+    __host__ __device__ int count() const { return ncx * ncy * ncz; }
+};
+
+__host__ __device__ inline Columns columns_of(Grid g) {
+    return Columns{(g.nx + PX - 1) / PX, (g.ny + PY - 1) / PY, (g.nz + kPlaneChunk - 1) / kPlaneChunk};
+}
+
 // d = dhat - sum_j beta_j d_(k-1-j) (classical Gram-Schmidt in the A inner
 // product; equal to the paper's sequential update because the directions in
 // the window are already mutually A-orthogonal), A d, and the partial dots
@@ -1498,8 +1522,8 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
                                                   State* st, const double* __restrict__ dots, int dnparts, int sl0,
                                                   int sl1, int sl2, int sl3, double* __restrict__ partials) {
     if (st->done) return;
-    __shared__ uint32_t lab_s[kHaloP];
-    __shared__ T d_s[kHaloP];
+    __shared__ uint32_t lab_s[2][kPlaneP];
+    __shared__ T d_s[2][kPlaneP];
     __shared__ double beta_s[kMaxOrtho];
     const int nprev = st->nprev;
     T bj[kMaxOrtho] = {T(0), T(0), T(0), T(0)};
@@ -1523,77 +1547,87 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         for (int j = 0; j < kMaxOrtho; ++j) bj[j] = (T)beta_s[j];
     }
     const T* pp[kMaxOrtho] = {p0, p1, p2, p3};
-    const Tiles tl = tiles_of(g);
-    const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
-    const int base = halo_base(lx, ly, lz);
+    const Columns cl = columns_of(g);
+    const int lx = threadIdx.x % PX, ly = threadIdx.x / PX;
+    const int own = (ly + 1) * PHX + (lx + 1);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
     struct LD {
         T dh;
         T p[NO > 0 ? NO : 1];
         uint8_t l;
     };
-    auto load = [&](int tile) {
-        const TileOrigin o = tile_origin(tile, tl);
-        return load_batch<kHalo, LD>([&](int i) {
-            const HaloCell c = halo_cell(g, o, i);
-            LD e;
-            e.dh = *at_or(dhat, c.q, c.in, pad_zero<T>());
+    auto element = [&](int zz, int yy, int xx) {
+        const bool in = in_grid(g, zz, yy, xx);
+        const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
+        LD e;
+        e.dh = *at_or(dhat, q, in, pad_zero<T>());
 #pragma unroll
-            for (int j = 0; j < NO; ++j) e.p[j] = *at_or(pp[j], c.q, c.in, pad_zero<T>());
-            e.l = *at_or(lab, c.q, c.in, g_pad_solid);
-            return e;
-        });
+        for (int j = 0; j < NO; ++j) e.p[j] = *at_or(pp[j], q, in, pad_zero<T>());
+        e.l = *at_or(lab, q, in, g_pad_solid);
+        return e;
     };
-    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
-        const TileOrigin o = tile_origin(tile, tl);
-        __syncthreads();
-        put_batch(pre, [&](int i, LD e) {
-            T dv = e.dh;
+    auto plane = [&](int x0, int y0, int zz) {
+        return load_batch<kPlane, LD>([&](int i) { return element(zz, y0 + i / PHX - 1, x0 + i % PHX - 1); });
+    };
+    auto direction = [&](const LD& e) {   // d = dhat - sum_j beta_j d_(k-1-j)
+        T dv = e.dh;
 #pragma unroll
-            for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * e.p[j] : dv;
-            d_s[i] = dv;
-            lab_s[i] = e.l;
-        });
-        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
-        const bool active = in_grid(g, zz, yy, xx);
-        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        const T rv = r[idx];
-        prefetch();
-        __syncthreads();
-        if (active) {
-            const T dv = d_s[base];
-            const T ad = apply_A<T, T, uint32_t>(lab_s, d_s, base, HX, HX * HY);
-            dout[idx] = dv;
-            adout[idx] = ad;
-            v[0] += (double)dv * (double)ad;
-            v[1] += (double)rv * (double)dv;
+        for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * e.p[j] : dv;
+        return dv;
+    };
+    for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int w = sp.t0;
+        const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * kPlaneChunk;
+        const int z1 = min(z0 + kPlaneChunk, g.nz);
+        const int xx = x0 + lx, yy = y0 + ly;
+        const bool col = xx < g.nx && yy < g.ny;
+        const LD below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
+        auto pre = plane(x0, y0, z0);
+        T dm = direction(below);   // own column, plane s - 2
+        uint32_t lm = below.l;
+        T rv = T(0);               // r of plane s - 1
+        for (int s = z0; s <= z1; ++s) {
+            const int cur = s & 1, prev = cur ^ 1;
+            __syncthreads();   // the reads of this buffer (plane s - 2) are done
+            put_batch(pre, [&](int i, LD e) {
+                d_s[cur][i] = direction(e);
+                lab_s[cur][i] = e.l;
+            });
+            const T rnext = r[col && s < z1 ? cell_index(g, s, yy, xx) : 0];
+            if (s < z1) pre = plane(x0, y0, s + 1);
+            __syncthreads();   // plane s is staged
+            if (s > z0) {      // the own cell of plane s - 1
+                const T dv = d_s[prev][own];
+                const uint32_t lc = lab_s[prev][own];
+                if (col) {
+                    T ad = T(0);
+                    if (lc == kFluid) {   // the mixed-BC 7-point row, neighbours z-, z+, y-, y+, x-, x+
+                        const uint32_t nl[6] = {lm, lab_s[cur][own], lab_s[prev][own - PHX], lab_s[prev][own + PHX],
+                                                lab_s[prev][own - 1], lab_s[prev][own + 1]};
+                        const T nv[6] = {dm, d_s[cur][own], d_s[prev][own - PHX], d_s[prev][own + PHX],
+                                         d_s[prev][own - 1], d_s[prev][own + 1]};
+                        int cnt = 0;
+                        T sum = T(0);
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) {
+                            cnt += (nl[k] != (uint32_t)kSolid);
+                            if (nl[k] == (uint32_t)kFluid) sum += nv[k];
+                        }
+                        ad = (T)cnt * dv - sum;
+                    }
+                    const size_t q = cell_index(g, s - 1, yy, xx);
+                    dout[q] = dv;
+                    adout[q] = ad;
+                    v[0] += (double)dv * (double)ad;
+                    v[1] += (double)rv * (double)dv;
+                }
+                dm = dv;
+                lm = lc;
+            }
+            rv = rnext;
         }
-    }, st);
+    }
     block_partials<kBlock>(v, partials);
-}
-
-// ---------------------------------------------------------------------------
-// plane-marching geometry of the 7-point kernels
-// ---------------------------------------------------------------------------
-// A block owns a footprint of PX x PY columns (one thread per column) and
-// marches it through kPlaneChunk z-planes.  Each plane is staged once, with
-// its x/y border, in rows of PX + 2 contiguous cells; the z neighbours of a
-// cell come from the planes staged before and after its own.  Against a
-// tile with a full 3-D halo this stages about 0.6x the elements, in rows
-// 3.7x longer.
-constexpr int PX = 64, PY = kBlock / PX;
-constexpr int PHX = PX + 2, PHY = PY + 2;
-constexpr int kPlane = PHX * PHY;
-constexpr int kPlaneP = pad_block(kPlane);
-constexpr int kPlaneChunk = 8;
-
-struct Columns {   // column footprints x z-chunks of a grid
-    int ncx, ncy, ncz;
-    __host__ __device__ int count() const { return ncx * ncy * ncz; }
-};
-
-__host__ __device__ inline Columns columns_of(Grid g) {
-    return Columns{(g.nx + PX - 1) / PX, (g.ny + PY - 1) / PY, (g.nz + kPlaneChunk - 1) / kPlaneChunk};
 }
 
 // The start of an iteration (Alg. 1): applies the pending update
