@@ -72,14 +72,20 @@ Grid level_grid(nps_dims d, int level) {  // level 1 = finest
     return Grid{d.nz >> s, d.ny >> s, d.nx >> s};
 }
 
+// Positive dims and at most 1e9 cells (cell indices are formed in 32 bits).
+int check_grid(nps_dims d) {
+    if (d.nz <= 0 || d.ny <= 0 || d.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    if ((double)d.nz * d.ny * d.nx > 1.0e9) return fail(NPS_ESHAPE, "grid too large");
+    return NPS_OK;
+}
+
 int check_dims(nps_dims d, int levels) {
     if (levels < 2 || levels > kMaxLevels)
         return fail(NPS_EINVAL, "levels must be in [2, %d], got %d", kMaxLevels, levels);
-    if (d.nz <= 0 || d.ny <= 0 || d.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    NPS_TRY(check_grid(d));
     const int m = 1 << (levels - 1);
     if (d.nz % m || d.ny % m || d.nx % m)
         return fail(NPS_ESHAPE, "dims (%d,%d,%d) not divisible by 2^(levels-1) = %d", d.nz, d.ny, d.nx, m);
-    if ((double)d.nz * d.ny * d.nx > 1.0e9) return fail(NPS_ESHAPE, "grid too large");
     return NPS_OK;
 }
 
@@ -1527,7 +1533,7 @@ int nps_solve(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const 
 int nps_apply_laplacian(const uint8_t* labels_d, nps_dims dims, const void* x_d, void* y_d, int precision,
                         void* stream) {
     if (!labels_d || !x_d || !y_d) return fail(NPS_EINVAL, "null argument");
-    if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    NPS_TRY(check_grid(dims));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Grid g{dims.nz, dims.ny, dims.nx};
     const int grid = std::min(tile_grid(g), 65536);
@@ -1740,7 +1746,7 @@ size_t nps_lanczos_workspace_bytes(nps_dims dims, int m) {
 int nps_lanczos(const uint8_t* labels_d, nps_dims dims, int m, int reorth, const double* v0_d, double* V_d,
                 double* alpha_d, double* beta_d, int* steps_h, void* ws_d, size_t ws_bytes, void* stream) {
     if (!labels_d || !v0_d || !V_d || !alpha_d || !beta_d || !steps_h || !ws_d) return fail(NPS_EINVAL, "null argument");
-    if (dims.nz <= 0 || dims.ny <= 0 || dims.nx <= 0) return fail(NPS_ESHAPE, "dims must be positive");
+    NPS_TRY(check_grid(dims));
     const size_t n = (size_t)dims.nz * dims.ny * dims.nx;
     if (m < 1 || n > (size_t)INT32_MAX) return fail(NPS_EINVAL, "need m >= 1 and fewer than 2^31 cells");
     const LanczosLayout L = lanczos_layout(n, m);

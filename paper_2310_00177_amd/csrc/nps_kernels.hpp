@@ -102,8 +102,10 @@ __device__ __forceinline__ TileOrigin tile_origin(int tile, Tiles tl) {
     return o;
 }
 
+// Grids hold at most 1e9 cells (the entry points check), so the index of an
+// in-grid cell is formed in 32 bits.
 __device__ __forceinline__ size_t cell_index(Grid g, int z, int y, int x) {
-    return ((size_t)z * g.ny + y) * g.nx + x;
+    return (size_t)(uint32_t)((z * g.ny + y) * g.nx + x);
 }
 
 __device__ __forceinline__ bool in_grid(Grid g, int z, int y, int x) {
@@ -1130,9 +1132,11 @@ __device__ __forceinline__ InterpSlots interp_slots() {
     return sl;
 }
 
+// (1 - w) lo + w hi, as lo + w (hi - lo); w = 1/4 when lo is the own cell
+// (odd fine coordinate), 3/4 when hi is.
 template <class T>
-__device__ __forceinline__ T interp_lerp(T lo, T hi, bool odd) {   // odd: lo is the own cell
-    return odd ? T(0.75) * lo + T(0.25) * hi : T(0.25) * lo + T(0.75) * hi;
+__device__ __forceinline__ T interp_lerp(T lo, T hi, T w) {
+    return fma(w, hi - lo, lo);
 }
 
 template <class T>
@@ -1154,10 +1158,11 @@ __device__ __forceinline__ void interp_tile(T* r_s, const T* c_s, Grid g, TileOr
         T v = T(0);
         if (in) {
             const T* c = c_s + (w & 1023u);
-            const bool ox = (w >> 10) & 1, oy = (w >> 11) & 1, oz = (w >> 12) & 1;
-            const T p00 = interp_lerp(c[0], c[1], ox), p01 = interp_lerp(c[DY], c[DY + 1], ox);
-            const T p10 = interp_lerp(c[DZ], c[DZ + 1], ox), p11 = interp_lerp(c[DZ + DY], c[DZ + DY + 1], ox);
-            v = interp_lerp(interp_lerp(p00, p01, oy), interp_lerp(p10, p11, oy), oz);
+            const T wx = (w >> 10) & 1 ? T(0.25) : T(0.75), wy = (w >> 11) & 1 ? T(0.25) : T(0.75),
+                    wz = (w >> 12) & 1 ? T(0.25) : T(0.75);
+            const T p00 = interp_lerp(c[0], c[1], wx), p01 = interp_lerp(c[DY], c[DY + 1], wx);
+            const T p10 = interp_lerp(c[DZ], c[DZ + 1], wx), p11 = interp_lerp(c[DZ + DY], c[DZ + DY + 1], wx);
+            v = interp_lerp(interp_lerp(p00, p01, wy), interp_lerp(p10, p11, wy), wz);
         }
         r_s[i] = v;
     }
