@@ -1270,9 +1270,11 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
             if (img_s[base] == (uint32_t)kFluid) out = (c1 * x1v + c2 * x2) * scale;
             dhat[idx] = out;
             if (x2out) x2out[idx] = x2;
-            if (!HOOK) {
+            if (!HOOK) {   // only the state's ndots slots (a uniform count)
+                const double od = (double)out;
 #pragma unroll
-                for (int j = 0; j < kMaxOrtho; ++j) v[j] += j < ndots ? (double)out * (double)adv[j] : 0.0;
+                for (int j = 0; j < kMaxOrtho; ++j)
+                    if (j < ndots) v[j] = fma(od, (double)adv[j], v[j]);
             }
         }
     }, st);
