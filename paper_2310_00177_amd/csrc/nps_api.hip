@@ -612,14 +612,12 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
     return NPS_OK;
 }
 
-// Level-1 down kernel.  HOOK: network only (r is the input).  *nparts (if
-// given) receives its grid, the number of partials it writes.
-template <class T, class X, bool HOOK>
+// Level-1 down kernel: x1 = CConv_1(r), r^2 = Pool(x1), r the network input.
+template <class T>
 int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
-                const double* b, X* xb0, X* xb1, const T* dpend, T* r, hipStream_t s, int* nparts = nullptr) {
+                const T* r, hipStream_t s) {
     const Grid g = level_grid(d, 1);
     State* st = mptr<State>(ws, lay.state);
-    double* partials = mptr<double>(ws, lay.partials);
     T* x1 = mptr<T>(ws, lay.x1[1]);
     T* rnext = mptr<T>(ws, lay.rb[2]);
     const CConvW<T>* w = cconv_block<T>(net, block_down(1));
@@ -627,11 +625,10 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
     const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k1[1]) : nullptr;
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        const int grid = persist_grid(&k_down_l1<T, X, KM, HOOK>, g);
-        if (nparts) *nparts = grid;
+        const int grid = persist_grid(&k_down_l1<T, KM>, g);
         return launch("net_down_l1", (double)ncells(g), s, [&] {
-            k_down_l1<T, X, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, b, xb0, xb1, dpend, r, x1, rnext, w, wm, kst, st,
-                                                              partials, cptr<int8_t>(ws, lay.wmode[1][0]));
+            k_down_l1<T, KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, kst, st,
+                                                     cptr<int8_t>(ws, lay.wmode[1][0]));
         });
     });
 }
@@ -877,7 +874,7 @@ struct SolverT : Solver {
             NPS_TRY(launch("control", 0, s, [&] {
                 k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_res, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
             }));
-        NPS_TRY((run_down_l1<T, X, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr, r, s)));
+        NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s));
         if (res_in_bottom) NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2, partials, np_res, hf_d));
         else NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
         NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
@@ -980,8 +977,7 @@ int precond_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const T*
     State* st = mptr<State>(ws, lay.state);
     NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0, 0); }));
     NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
-    NPS_TRY((run_down_l1<T, T, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr,
-                                     const_cast<T*>(r_in), s)));
+    NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r_in, s));
     const T* x2 = nullptr;
     NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
     const T* none[kMaxOrtho] = {nullptr, nullptr, nullptr, nullptr};
@@ -1249,7 +1245,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         else
             NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<false><<<kSumBlocks, kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
     }
-    NPS_TRY((run_down_l1<T, T, true>(net, labels, d, plan, lay, ws, nullptr, nullptr, nullptr, nullptr, const_cast<T*>(r), s)));
+    NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s));
     for (int l = 2; l <= L; ++l) {
         const Grid g = level_grid(d, l);
         const int grid = tile_grid(g);

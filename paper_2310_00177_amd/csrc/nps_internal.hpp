@@ -103,14 +103,12 @@ struct State {
 constexpr int TX = 16, TY = 4, TZ = 4;
 constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
 constexpr int kHalo = HX * HY * HZ;
-constexpr int H2X = TX + 4, H2Y = TY + 4, H2Z = TZ + 4;
-constexpr int kHalo2 = H2X * H2Y * H2Z;
 static_assert(TX * TY * TZ == kBlock, "one cell per thread");
 
 // LDS arrays filled by a batched staging hold whole rounds of kBlock elements
 // (the surplus of the last round lands in the padding).
 constexpr int pad_block(int n) { return (n + kBlock - 1) / kBlock * kBlock; }
-constexpr int kHaloP = pad_block(kHalo), kHalo2P = pad_block(kHalo2);
+constexpr int kHaloP = pad_block(kHalo);
 
 struct Tiles {
     int ntx, nty, ntz;

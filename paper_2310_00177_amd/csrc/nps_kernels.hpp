@@ -853,15 +853,11 @@ __device__ __forceinline__ void pool_tile_to(const T* out_s, TileOrigin o, Grid 
     }
 }
 
-// Level 1, first kernel of an iteration.  SOLVE: applies the pending update
-// x += alpha d, forms the literal residual r = b - A x over the tile and its
-// one-cell halo (x staged with a two-cell halo), writes x and r of the tile's
-// cells and their partial ||r||^2.  x is read from one of the two solution
-// buffers and written to the other (state.xcur selects), so no block reads a
-// value another block has already updated.  HOOK (nps_apply_precond): r is
-// the input, masked to fluid.  Then x1 = CConv_1^1(r) and r^2 = Pool(x1).
+// Level 1 of the down sweep: x1 = CConv_1^1(r) and r^2 = Pool(x1), with r
+// the network input (masked to fluid: the solve's residual is zero off
+// fluid already, nps_apply_precond's input need not be).
 template <class X, class T>
-struct XDL {   // x, the pending direction and the label of one haloed cell
+struct XDL {   // x, the pending direction and the label of one staged cell
     X x;
     T d;
     uint8_t l;
@@ -873,103 +869,41 @@ struct RL {    // network input and label of one haloed cell
     uint8_t l;
 };
 
-template <class X, class T>
-struct DownL1Loads {
-    Batch<kHalo2, XDL<X, T>> h2;   // two-cell halo
-    Batch<kHalo, double> b;        // b over the one-cell halo
-};
-
-template <class T, class X, int KM, bool HOOK>
+template <class T, int KM>
 __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
-    const uint8_t* __restrict__ lab, Grid g, const double* __restrict__ b, X* xb0, X* xb1,
-    const T* __restrict__ dpend, T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
-    const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst,
-    const State* st, double* partials, const int8_t* __restrict__ wmode) {
+    const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ r, T* __restrict__ x1, T* __restrict__ rnext,
+    const CConvW<T>* __restrict__ w, const MfmaW* __restrict__ wm, const T* __restrict__ kst, const State* st,
+    const int8_t* __restrict__ wmode) {
     __shared__ uint32_t img_s[kHaloP];
     __shared__ uint32_t feat_s[is_mfma(KM) ? kHaloP : 1];
     __shared__ T r_s[kHaloP];
     __shared__ T out_s[kBlock];
-    __shared__ uint8_t lab2_s[HOOK ? 1 : kHalo2P];
-    __shared__ X x2_s[HOOK ? 1 : kHalo2P];
-    __shared__ double b_s[HOOK ? 1 : kHaloP];
-    const bool pend = !HOOK && st->pending;
-    const X alpha = HOOK ? X(0) : (X)st->alpha;
-    const int cur = HOOK ? 0 : st->xcur;
-    const X* __restrict__ x = cur ? xb1 : xb0;
-    X* __restrict__ xnew = cur ? xb0 : xb1;
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
     const MfmaCtx<KM> mc = mfma_ctx<KM>(wm, lz);
-    double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
     auto load = [&](int tile) {
         const TileOrigin o = tile_origin(tile, tl);
-        if constexpr (HOOK) {
-            return load_batch<kHalo, RL<T>>([&](int i) {
-                const HaloCell c = halo_cell(g, o, i);
-                return RL<T>{*at_or(r, c.q, c.in, pad_zero<T>()), *at_or(lab, c.q, c.in, g_pad_solid)};
-            });
-        } else {
-            DownL1Loads<X, T> ld;
-            ld.h2 = load_batch<kHalo2, XDL<X, T>>([&](int i) {
-                const int xx = o.x0 + i % H2X - 2, yy = o.y0 + (i / H2X) % H2Y - 2, zz = o.z0 + i / (H2X * H2Y) - 2;
-                const bool in = in_grid(g, zz, yy, xx);
-                const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
-                return XDL<X, T>{*at_or<X>(x, q, in, pad_zero<X>()), *at_or(dpend, q, in, pad_zero<T>()),
-                                 *at_or(lab, q, in, g_pad_solid)};
-            });
-            ld.b = load_batch<kHalo, double>([&](int i) {
-                const HaloCell c = halo_cell(g, o, i);
-                return *at_or(b, c.q, c.in, pad_zero<double>());
-            });
-            return ld;
-        }
+        return load_batch<kHalo, RL<T>>([&](int i) {
+            const HaloCell c = halo_cell(g, o, i);
+            return RL<T>{*at_or(r, c.q, c.in, pad_zero<T>()), *at_or(lab, c.q, c.in, g_pad_solid)};
+        });
     };
-    const bool ran = tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
+    tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
         __syncthreads();
-        if constexpr (HOOK) {
-            put_batch(pre, [&](int i, RL<T> e) {
-                r_s[i] = e.l == kFluid ? e.r : T(0);
-                img_s[i] = e.l;
-                if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(e.l);
-            });
-            prefetch();
-        } else {
-            // x (+ alpha d) and labels over the two-cell halo, b over the one-cell halo
-            put_batch(pre.h2, [&](int i, XDL<X, T> e) {
-                lab2_s[i] = e.l;
-                x2_s[i] = pend ? e.x + alpha * (X)e.d : e.x;
-            });
-            put_batch(pre.b, [&](int i, double bv) { b_s[i] = bv; });
-            prefetch();
-            __syncthreads();
-            // r = b - A x over the tile and its one-cell halo (zero off fluid /
-            // off grid); the labels of the same cells become the image.
-            for (int i = threadIdx.x; i < kHalo; i += kBlock) {
-                const int hx = i % HX, hy = (i / HX) % HY, hz = i / (HX * HY);
-                const int b2 = ((hz + 1) * H2Y + (hy + 1)) * H2X + (hx + 1);
-                const uint8_t l = lab2_s[b2];
-                double rv = 0.0;
-                if (l == kFluid) rv = b_s[i] - apply_A<double, X, uint8_t>(lab2_s, x2_s, b2, H2X, H2X * H2Y);
-                r_s[i] = (T)rv;
-                img_s[i] = l;
-                if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(l);
-            }
-        }
+        put_batch(pre, [&](int i, RL<T> e) {
+            r_s[i] = e.l == kFluid ? e.r : T(0);
+            img_s[i] = e.l;
+            if constexpr (is_mfma(KM)) feat_s[i] = feat_word<KM, true>(e.l);
+        });
+        prefetch();
         __syncthreads();
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
-        if (!HOOK && active) {
-            const int b2 = ((lz + 2) * H2Y + (ly + 2)) * H2X + (lx + 2);
-            xnew[idx] = x2_s[b2];
-            const T rv = r_s[base];
-            r[idx] = rv;
-            v[0] += (double)rv * (double)rv;
-        }
         const int mode = wave_mode<true>(wmode, wm_e, active, img_s, base, 1u, true, false);
         const T out = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
         if (active) x1[idx] = out;
@@ -977,7 +911,6 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
         __syncthreads();
         pool_tile_to<T>(out_s, o, g, rnext);
     }, st);
-    if (!HOOK && ran) block_partials<kBlock>(v, partials);
 }
 
 // x1 = CConv_1(r, I) on one level l >= 2, and (POOL) r_next = Pool(x1).
