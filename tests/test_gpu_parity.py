@@ -294,3 +294,22 @@ def test_benchmark_workload_solve(precision):
     print(f"128^3 {precision}: {info.iterations} its, reported {info.rel_residual:.3e}, oracle {true_rel:.3e}", flush=True)
     assert info.status == 0 and true_rel < 1e-6
     assert info.rel_residual == pytest.approx(true_rel, rel=1e-3)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_ragged_column_footprints_match_oracle(precision):
+    """10 x 6 x 70 with L = 2: the plane-marching kernels see a partial
+    64-column footprint in x, a partial 4-row footprint in y and a 2-plane
+    last z-chunk; the k-th iterate matches the oracle's."""
+    shape = (10, 6, 70)
+    lab = random_labels(shape, seed=31)
+    b = gi.gen_rhs(lab, seed=32)
+    params = gi.multilevel_params(2)
+    P = onet.Network(params, 2, lab)
+    p, tol = (nps.FP64, 1e-9) if precision == "fp64" else (nps.FP32, 1e-4)
+    for k in (1, 4):
+        print(f"ragged footprints {precision} k={k}", flush=True)
+        ref = onpsdo.solve(lab, b, P.apply, max_iter=k, fixed_iters=True)
+        x, info = nps.solve(nps.Net(params, 2), dev(lab), dev(b), max_iter=k, fixed_iters=True, precision=p)
+        assert info.iterations == k
+        assert rel_err(x.cpu().numpy(), ref.x) <= tol, (k, rel_err(x.cpu().numpy(), ref.x))
