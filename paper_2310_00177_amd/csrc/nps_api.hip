@@ -500,7 +500,7 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     for (int l = 1; l <= L; ++l) {
         if (plan.km[l] != kStored) continue;
         const Grid g = level_grid(d, l);
-        const int grid = elem_grid(ncells(g));
+        const int grid = elem_grid((size_t)kTaps * ncells(g));   // one thread per (tap, cell)
         for (int which = 0; which < (l < L ? 2 : 1); ++which) {
             T* out = mptr<T>(ws, which == 0 ? lay.k1[l] : lay.k2[l]);
             const CConvW<double>* w = cconv_block<double>(net, which == 0 ? block_down(l) : block_up(net, l));

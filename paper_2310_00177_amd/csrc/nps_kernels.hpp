@@ -583,33 +583,62 @@ __global__ __launch_bounds__(kBlock) void k_pool_counts(const void* __restrict__
     }
 }
 
-// The image-window sums of Aff_1^l and Aff_2^l (global means), in double.
+// The image-window sums of Aff_1^l and Aff_2^l (global means), in double:
+// S = sum_p sum_o sum_c w[c][o] i_c(p + o), the image solid outside the grid.
+// With q = p + o the in-grid part is sum_q sum_c i_c(q) W_c(q), where
+// W_c(q) = sum of w[c][o] over the o with q - o in the grid (all 27 for an
+// interior cell), so each cell is read once; the out-of-grid part is
+// sum_o w[solid][o] (n - #{p : p + o in the grid}), with that count the
+// product over the axes of (N_a - |o_a|), added by one thread.
 template <bool L1>
 __global__ __launch_bounds__(kBlock) void k_aff(const void* __restrict__ img, Grid g, double inv_full,
                                                 const AffW* __restrict__ a1, const AffW* __restrict__ a2,
                                                 double* partials) {
     const size_t n = ncells(g);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    __shared__ double full_s[6];   // W_c of an interior cell, for Aff_1 and Aff_2
+    if (threadIdx.x < 6) {
+        const AffW* a = threadIdx.x < 3 ? a1 : a2;
+        double t = 0.0;
+        for (int o = 0; o < kTaps; ++o) t += a->w[threadIdx.x % 3][o];
+        full_s[threadIdx.x] = t;
+    }
+    __syncthreads();
+    const double full1[3] = {full_s[0], full_s[1], full_s[2]}, full2[3] = {full_s[3], full_s[4], full_s[5]};
     for (size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (size_t)gridDim.x * kBlock) {
         const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
-        for (int o = 0; o < kTaps; ++o) {
-            const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
-            double i0 = 0.0, i1 = 0.0, i2 = 1.0;   // solid padding
-            if (in_grid(g, qz, qy, qx)) {
-                const size_t q = cell_index(g, qz, qy, qx);
-                if (L1) {
-                    const uint8_t l = static_cast<const uint8_t*>(img)[q];
-                    i0 = l == kFluid;
-                    i1 = l == kAir;
-                } else {
-                    const uint32_t c = static_cast<const uint32_t*>(img)[q];
-                    i0 = (double)(c & 0xffffu) * inv_full;
-                    i1 = (double)(c >> 16) * inv_full;
+        double i0, i1;
+        if (L1) {
+            const uint8_t l = static_cast<const uint8_t*>(img)[p];
+            i0 = l == kFluid;
+            i1 = l == kAir;
+        } else {
+            const uint32_t c = static_cast<const uint32_t*>(img)[p];
+            i0 = (double)(c & 0xffffu) * inv_full;
+            i1 = (double)(c >> 16) * inv_full;
+        }
+        const double i2 = 1.0 - i0 - i1;
+        double W1[3] = {full1[0], full1[1], full1[2]}, W2[3] = {full2[0], full2[1], full2[2]};
+        const bool interior = x >= 1 && y >= 1 && z >= 1 && x + 1 < g.nx && y + 1 < g.ny && z + 1 < g.nz;
+        if (!interior) {
+            for (int c = 0; c < 3; ++c) W1[c] = W2[c] = 0.0;
+            for (int o = 0; o < kTaps; ++o) {
+                if (!in_grid(g, z - (o / 9 - 1), y - ((o / 3) % 3 - 1), x - (o % 3 - 1))) continue;
+                for (int c = 0; c < 3; ++c) {
+                    W1[c] += a1->w[c][o];
+                    W2[c] += a2->w[c][o];
                 }
-                i2 = 1.0 - i0 - i1;
             }
-            v[0] += a1->w[0][o] * i0 + a1->w[1][o] * i1 + a1->w[2][o] * i2;
-            v[1] += a2->w[0][o] * i0 + a2->w[1][o] * i1 + a2->w[2][o] * i2;
+        }
+        v[0] += i0 * W1[0] + i1 * W1[1] + i2 * W1[2];
+        v[1] += i0 * W2[0] + i1 * W2[1] + i2 * W2[2];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {   // the solid padding
+        for (int o = 0; o < kTaps; ++o) {
+            const double in = (double)max(g.nz - abs(o / 9 - 1), 0) * (double)max(g.ny - abs((o / 3) % 3 - 1), 0) *
+                              (double)max(g.nx - abs(o % 3 - 1), 0);
+            v[0] += a1->w[2][o] * ((double)n - in);
+            v[1] += a2->w[2][o] * ((double)n - in);
         }
     }
     block_partials<kBlock>(v, partials);
@@ -619,11 +648,15 @@ __global__ __launch_bounds__(kBlock) void k_aff(const void* __restrict__ img, Gr
 template <class T, bool L1>
 __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ img, Grid g,
                                                        const CConvW<double>* __restrict__ w, T* __restrict__ kst) {
+    // one thread per (tap t, cell p), i = t n + p: the taps of a block share
+    // their weights (uniform loads), the stores are contiguous; each tap sums
+    // its 27 window terms in the same order as a per-cell loop would
     const size_t n = ncells(g);
-    for (size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (size_t)gridDim.x * kBlock) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < (size_t)kTaps * n; i += (size_t)gridDim.x * kBlock) {
+        const int t = (int)(i / n);
+        const size_t p = i - (size_t)t * n;
         const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
-        double K[kTaps];
-        for (int t = 0; t < kTaps; ++t) K[t] = w->C[t];
+        double K = w->C[t];
         for (int o = 0; o < kTaps; ++o) {
             const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
             uint32_t c0 = 0, c1 = 0;   // solid padding: no fluid, no air
@@ -632,9 +665,9 @@ __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ 
                 const uint32_t v = L1 ? (uint32_t)static_cast<const uint8_t*>(img)[q] : static_cast<const uint32_t*>(img)[q];
                 counts_of<L1>(v, c0, c1);
             }
-            for (int t = 0; t < kTaps; ++t) K[t] += w->D[o][t][0] * (double)c0 + w->D[o][t][1] * (double)c1;
+            K += w->D[o][t][0] * (double)c0 + w->D[o][t][1] * (double)c1;
         }
-        for (int t = 0; t < kTaps; ++t) kst[(size_t)t * n + p] = (T)K[t];
+        kst[i] = (T)K;
     }
 }
 
