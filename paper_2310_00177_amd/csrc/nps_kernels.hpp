@@ -547,9 +547,9 @@ __global__ __launch_bounds__(kBlock) void k_scan(const uint8_t* __restrict__ lab
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};   // bb, n_fluid, bad labels, non-finite
     for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) {
         const uint8_t l = lab[i];
+        const double bv = b[i];   // read with the label (used on fluid cells only)
         if (l > kSolid) v[2] += 1.0;
         if (l == kFluid) {
-            const double bv = b[i];
             v[1] += 1.0;
             if (!isfinite(bv)) v[3] += 1.0;
             else v[0] += bv * bv;
