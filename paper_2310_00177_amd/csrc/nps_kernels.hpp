@@ -657,15 +657,18 @@ __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ 
         const size_t p = i - (size_t)t * n;
         const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
         double K = w->C[t];
+#pragma unroll
         for (int o = 0; o < kTaps; ++o) {
+            // solid padding (no fluid, no air) outside the grid: the cell itself is
+            // read there and its weights zeroed, so the 27 reads are unconditional
             const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
-            uint32_t c0 = 0, c1 = 0;   // solid padding: no fluid, no air
-            if (in_grid(g, qz, qy, qx)) {
-                const size_t q = cell_index(g, qz, qy, qx);
-                const uint32_t v = L1 ? (uint32_t)static_cast<const uint8_t*>(img)[q] : static_cast<const uint32_t*>(img)[q];
-                counts_of<L1>(v, c0, c1);
-            }
-            K += w->D[o][t][0] * (double)c0 + w->D[o][t][1] * (double)c1;
+            const bool in = in_grid(g, qz, qy, qx);
+            const size_t q = in ? cell_index(g, qz, qy, qx) : p;
+            const uint32_t v = L1 ? (uint32_t)static_cast<const uint8_t*>(img)[q] : static_cast<const uint32_t*>(img)[q];
+            uint32_t c0, c1;
+            counts_of<L1>(v, c0, c1);
+            const double m = in ? 1.0 : 0.0;
+            K += (w->D[o][t][0] * m) * (double)c0 + (w->D[o][t][1] * m) * (double)c1;
         }
         kst[i] = (T)K;
     }
