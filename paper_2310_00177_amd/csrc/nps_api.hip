@@ -824,8 +824,21 @@ struct SolverT : Solver {
         return run_setup<T>(net, labels, d, plan, lay, ws, s);
     }
 
-    // Body k forms x_(k-1) and r_(k-1) = b - A x_(k-1) (applying step k-1),
-    // tests convergence, then forms the direction d_k and its step alpha_k.
+    // The ortho kernel's grid (the count of its partials, which the next
+    // body's residual kernel sums).
+    int ortho_grid(Grid g) const {
+        switch (o.n_ortho) {
+            case 0: return persist_grid_n(&k_ortho<T, 0>, columns_of(g).count());
+            case 1: return persist_grid_n(&k_ortho<T, 1>, columns_of(g).count());
+            case 2: return persist_grid_n(&k_ortho<T, 2>, columns_of(g).count());
+            case 3: return persist_grid_n(&k_ortho<T, 3>, columns_of(g).count());
+            default: return persist_grid_n(&k_ortho<T, 4>, columns_of(g).count());
+        }
+    }
+
+    // Body k finishes step k-1 (its length from the previous body's dots),
+    // forms x_(k-1) and r_(k-1) = b - A x_(k-1), tests convergence, then forms
+    // the direction d_k and the dots of its step.
     int enqueue_body(int k) override {
         const Grid g = level_grid(d, 1);
         const double cells = (double)ncells(g);
@@ -858,13 +871,17 @@ struct SolverT : Solver {
         const T* x2 = nullptr;
         int np = 0;
         // x += alpha d and r = b - A x (one-cell halo), then the network on r
+        // (from body 2 on it first runs the Step stage of the previous body, on
+        // the ortho kernel's partials; its own ||r||^2 partials go to the dots
+        // buffer, which the Residual stage consumes before the up kernel refills it)
         const int np_res = persist_grid_n(&k_residual<T, X>, columns_of(g).count());
+        const int snp = k > 1 ? ortho_grid(g) : 0;
         NPS_TRY(launch("residual", cells, s, [&] {
             // body k reads the iterate from buffer (k - 1) & 1 (state.xcur, which
             // every Residual stage flips) and writes the other
             const bool odd = ((k - 1) & 1) != 0;
             k_residual<T, X><<<np_res, kBlock, 0, s>>>(labels, g, b, odd ? x1b : x0, odd ? x0 : x1b, dpend, r, st,
-                                                       partials);
+                                                       partials, snp, ((k - 1) % R + R) % R, hf_d, pdots);
         }));
         // The Residual stage (convergence test, 1/||r||, the dots the up
         // kernel forms) is first needed by the up sweep, and the network is
@@ -872,10 +889,10 @@ struct SolverT : Solver {
         const bool res_in_bottom = plan.lb <= net->levels;
         if (!res_in_bottom)
             NPS_TRY(launch("control", 0, s, [&] {
-                k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, partials, np_res, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
+                k_control<kStageResidual><<<1, kCtlBlock, 0, s>>>(st, pdots, np_res, 0, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
             }));
         NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s));
-        if (res_in_bottom) NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2, partials, np_res, hf_d));
+        if (res_in_bottom) NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2, pdots, np_res, hf_d));
         else NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
         NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
         if (o.symmetric) {   // d^ = P^T P(r)/||r||, then the dots the up kernel left out
@@ -890,14 +907,7 @@ struct SolverT : Solver {
         }
         // the Dots stage runs inside the ortho kernel (every block sums the dots)
         const int dnp = o.n_ortho > 0 ? np : 0;
-        int ogrid = 0;
-        switch (o.n_ortho) {
-            case 0: ogrid = persist_grid_n(&k_ortho<T, 0>, columns_of(g).count()); break;
-            case 1: ogrid = persist_grid_n(&k_ortho<T, 1>, columns_of(g).count()); break;
-            case 2: ogrid = persist_grid_n(&k_ortho<T, 2>, columns_of(g).count()); break;
-            case 3: ogrid = persist_grid_n(&k_ortho<T, 3>, columns_of(g).count()); break;
-            default: ogrid = persist_grid_n(&k_ortho<T, 4>, columns_of(g).count()); break;
-        }
+        const int ogrid = ortho_grid(g);
         NPS_TRY(launch("ortho_matvec", cells, s, [&] {
             auto go = [&](auto no) {
                 k_ortho<T, decltype(no)::value><<<ogrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r,
@@ -912,9 +922,7 @@ struct SolverT : Solver {
                 default: go(std::integral_constant<int, 4>{}); break;
             }
         }));
-        NPS_TRY(launch("control", 0, s, [&] {
-            k_control<kStageStep><<<1, kCtlBlock, 0, s>>>(st, partials, ogrid, slot, 0, 0, 0, 0.0, 0.0, 0.0, hf_d);
-        }));
+        // the Step stage (alpha) runs at the start of the next body's residual kernel
         return NPS_OK;
     }
 

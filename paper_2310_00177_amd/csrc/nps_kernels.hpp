@@ -32,8 +32,7 @@ namespace nps {
 #define NPS_WAVES_PER_EU(n) __attribute__((amdgpu_waves_per_eu(n)))
 
 // The three-piece bf16 weights of the FP32 MFMA path need more registers.
-// (The level-1 down kernel, which also keeps the next tile's two-cell halo
-// in flight, runs at 3 in every mode.)
+// (Higher floors make the CConv kernels spill and run slower.)
 constexpr int waves_floor(int km) { return km == kMfmaBf16x3 ? 3 : 4; }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -788,6 +787,31 @@ __device__ __forceinline__ void host_flags(HostFlags* hf, int iter, int done) {
     h->done = done;
 }
 
+// The Step stage from d . A d and r . d: the step length (NPSDO: exact line
+// search; PCG forms: alpha = r . s / d . A d), or a breakdown when d . A d is
+// not positive or a dot is not finite.  step_alpha forms it without writing
+// the state; step_update also records it (i0: ring slot of the direction).
+__device__ __forceinline__ bool step_alpha(const State* st, double dAd, double rd, double& alpha) {
+    if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) return false;
+    alpha = (st->method == 0 ? rd : st->rho) / dAd;
+    return true;
+}
+
+__device__ __forceinline__ void step_update(State* st, int i0, double dAd, double rd, HostFlags* hf) {
+    double alpha;
+    st->dAd[i0] = dAd;
+    st->rd = rd;
+    if (!step_alpha(st, dAd, rd, alpha)) {
+        st->done = 1;
+        st->status = -6;   // NPS_EBREAKDOWN
+        if (hf) host_flags(hf, st->iter, 1);
+    } else {
+        st->alpha = alpha;
+        st->rho_prev = st->rho;
+        st->pending = 1;
+    }
+}
+
 // The state update of one stage from its summed partials v (one thread).
 // The stopping decision is mirrored to host memory (hf) for the host loop.
 // The Dots stage may run in every block of a kernel at once (each with the
@@ -836,19 +860,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
     } else if constexpr (STAGE == kStageLoss) {     // training loss: ||b - A y||^2
         st->rr = v[0];
     } else if constexpr (STAGE == kStageStep) {     // i0: ring slot of the new direction
-        const double dAd = v[0], rd = v[1];
-        st->dAd[i0] = dAd;
-        st->rd = rd;
-        if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) {
-            st->done = 1;
-            st->status = -6;   // NPS_EBREAKDOWN
-            if (hf) host_flags(hf, st->iter, 1);
-        } else {
-            // NPSDO: exact line search; PCG forms: alpha = r . s / d . A d
-            st->alpha = (st->method == 0 ? rd : st->rho) / dAd;
-            st->rho_prev = st->rho;
-            st->pending = 1;
-        }
+        step_update(st, i0, v[0], v[1], hf);
     }
 }
 
@@ -1614,16 +1626,24 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
 // network input, and the partial ||r||^2.  Plane-marching: step s stages
 // plane s (x + alpha d and the labels, outside the grid x = 0 and solid)
 // and forms plane s - 1.
+// With snp > 0 the kernel first runs the previous iteration's Step stage:
+// every block sums the snp partials of d . A d and r . d (the same sums in
+// each, a fixed order), forms alpha and applies the update; block 0 records
+// the stage (slot: ring slot of d); on a breakdown no block writes anything.
+// With snp == 0 (the first iteration) there is no pending update.
 template <class T, class X>
 __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__ lab, Grid g,
                                                      const double* __restrict__ b, const X* __restrict__ x,
                                                      X* __restrict__ xnew, const T* __restrict__ dpend,
-                                                     T* __restrict__ r, const State* st, double* partials) {
+                                                     T* __restrict__ r, State* st, const double* __restrict__ steps,
+                                                     int snp, int slot, HostFlags* hf, double* partials) {
     __shared__ uint32_t lab_s[2][kPlaneP];
     __shared__ X x_s[2][kPlaneP];
+    __shared__ double alpha_s;
+    __shared__ int ok_s;
     const int done = st->done;   // tested once the first loads are out
-    const bool pend = st->pending;
-    const X alpha = (X)st->alpha;
+    const bool pend = snp > 0;
+    X alpha = X(0);
     const Columns cl = columns_of(g);
     const int lx = threadIdx.x % PX, ly = threadIdx.x / PX;
     const int own = (ly + 1) * PHX + (lx + 1);
@@ -1651,6 +1671,19 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
             if (done) return;
             first = false;
+            if (pend) {   // the Step stage, its loads behind the first plane's
+                double v[2];
+                sum_partials<2, kBlock>(steps, snp, 2, v);
+                if (threadIdx.x == 0) {
+                    double a = 0.0;
+                    ok_s = step_alpha(st, v[0], v[1], a);
+                    alpha_s = a;
+                    if (blockIdx.x == 0) step_update(st, slot, v[0], v[1], hf);
+                }
+                __syncthreads();
+                if (!ok_s) return;
+                alpha = (X)alpha_s;
+            }
         }
         X xm = updated(below);   // own column, plane s - 2
         uint32_t lm = below.l;
