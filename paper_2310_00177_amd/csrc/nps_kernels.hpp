@@ -1471,7 +1471,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
 // plane-marching geometry of the 7-point kernels
 // ---------------------------------------------------------------------------
 // A block owns a footprint of PX x PY columns (one thread per column) and
-// marches it through kPlaneChunk z-planes.  Each plane is staged once, with
+// marches it through a chunk of z-planes.  Each plane is staged once, with
 // its x/y border, in rows of PX + 2 contiguous cells; the z neighbours of a
 // cell come from the planes staged before and after its own.  Against a
 // tile with a full 3-D halo this stages about 0.6x the elements, in rows
@@ -1480,15 +1480,20 @@ constexpr int PX = 64, PY = kBlock / PX;
 constexpr int PHX = PX + 2, PHY = PY + 2;
 constexpr int kPlane = PHX * PHY;
 constexpr int kPlaneP = pad_block(kPlane);
-constexpr int kPlaneChunk = 8;
-
 struct Columns {   // column footprints x z-chunks of a grid
-    int ncx, ncy, ncz;
+    int ncx, ncy, ncz, chunk;
     __host__ __device__ int count() const { return ncx * ncy * ncz; }
 };
 
+// Chunks of 8 planes (the plane below a chunk is read once more per chunk);
+// 4 or 2 on grids that would otherwise give fewer than 512 chunks, so that
+// small grids still spread over the compute units.  A function of the grid
+// alone: launches and kernels agree on it.
 __host__ __device__ inline Columns columns_of(Grid g) {
-    return Columns{(g.nx + PX - 1) / PX, (g.ny + PY - 1) / PY, (g.nz + kPlaneChunk - 1) / kPlaneChunk};
+    const int ncx = (g.nx + PX - 1) / PX, ncy = (g.ny + PY - 1) / PY;
+    int chunk = 8;
+    while (chunk > 2 && ncx * ncy * ((g.nz + chunk - 1) / chunk) < 512) chunk /= 2;
+    return Columns{ncx, ncy, (g.nz + chunk - 1) / chunk, chunk};
 }
 
 // d = dhat - sum_j beta_j d_(k-1-j) (classical Gram-Schmidt in the A inner
@@ -1565,8 +1570,8 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
     };
     for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int w = sp.t0;
-        const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * kPlaneChunk;
-        const int z1 = min(z0 + kPlaneChunk, g.nz);
+        const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
+        const int z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + lx, yy = y0 + ly;
         const bool col = xx < g.nx && yy < g.ny;
         const LD below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
@@ -1661,8 +1666,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
     bool first = true;
     for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int w = sp.t0;
-        const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * kPlaneChunk;
-        const int z1 = min(z0 + kPlaneChunk, g.nz);
+        const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
+        const int z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + lx, yy = y0 + ly;
         const bool col = xx < g.nx && yy < g.ny;
         const XDL<X, T> below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
