@@ -251,6 +251,7 @@ def test_errors_are_reported():
     assert e.value.code == -2
     x, info = nps.solve(nps.Net(np.zeros(gi.param_count(6)), 6), dev(lab), dev(b), check=False)
     assert info.status == -6 and info.iterations == 0
+    assert torch.all(x == 0)   # the last iterate: the step that broke down was not applied
     x, info = nps.solve(net, dev(lab), dev(b), max_iter=3)
     assert info.status == 1 and info.iterations == 3
     assert info.rel_residual == pytest.approx(lap.rel_residual(lab, b, x.cpu().numpy()), rel=1e-6)
