@@ -570,15 +570,28 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         BottomArgs<T> a = {};
         a.lb = plan.lb;
         a.L = L;
-        size_t cells = 0;
-        for (int l = plan.lb; l <= L; ++l) {
-            a.g[l] = level_grid(d, l);
-            a.k1[l] = cptr<T>(ws, lay.k1[l]);
-            a.k2[l] = l < L ? cptr<T>(ws, lay.k2[l]) : nullptr;
-            cells += ncells(a.g[l]);
-        }
         if (bottom_footprint(d, plan.lb, L) > (size_t)kBottomLds)
             return fail(NPS_EINVAL, "bottom levels exceed the workgroup buffer");
+        size_t cells = 0;
+        int off = 0;
+        for (int l = plan.lb; l <= L; ++l) {
+            const Grid g = level_grid(d, l);
+            const int pc = padded_cells(g);
+            BottomLevel& v = a.lv[l];
+            v.g = g;
+            v.n = (int)ncells(g);
+            v.sy = g.nx + 2;
+            v.sz = (g.ny + 2) * (g.nx + 2);
+            v.r = off;
+            v.x1 = off + pc;
+            v.mx = div_magic(g.nx);
+            v.mxy = div_magic(g.nx * g.ny);
+            off += 2 * pc;
+            a.k1[l] = cptr<T>(ws, lay.k1[l]);
+            a.k2[l] = l < L ? cptr<T>(ws, lay.k2[l]) : nullptr;
+            cells += ncells(g);
+        }
+        a.used = off;
         a.rin = cptr<T>(ws, lay.rb[plan.lb]);
         a.xout = mptr<T>(ws, lay.rb[plan.lb]);
         a.res_partials = res_partials;

@@ -1265,10 +1265,34 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
 // The smallest levels lb..L in one workgroup, in LDS, with stored kernels:
 // down sweep (CConv_1 + pool), coarsest CConv_1, up sweep (Interp + CConv_2 +
 // combine).  Reads r^lb, writes x^lb.
+
+// The bottom levels live in LDS with a one-cell zero border, so that every
+// CConv tap is a fixed offset with no bounds test.
+__host__ __device__ inline int padded_cells(Grid g) { return (g.nx + 2) * (g.ny + 2) * (g.nz + 2); }
+
+// Cell p of a bottom level (p < kBottomThreads <= 512) splits into (z, y, x)
+// by multiplies: with m = ceil(2^20 / d) = (2^20 + e) / d, 0 <= e < d,
+// (p m) >> 20 = floor(p / d + p e / (d 2^20)), and the added term is below
+// p / 2^20 < 1 / d for every d < 2048, too small to pass the next multiple
+// of 1 / d.  So (p m) >> 20 == p / d exactly.
+constexpr int kDivShift = 20;
+__host__ __device__ inline uint32_t div_magic(int d) { return (uint32_t)(((1u << kDivShift) + d - 1) / d); }
+
+// One bottom level as the kernel addresses it, set up on the host: one scalar
+// load per level per phase, no divisions and no running sums in the kernel.
+struct BottomLevel {
+    Grid g;
+    int n;              // cells
+    int sy, sz;         // padded strides of y and z
+    int r, x1;          // LDS offsets (elements) of the level's two padded slots
+    uint32_t mx, mxy;   // div_magic(nx), div_magic(nx * ny)
+};
+
 template <class T>
 struct BottomArgs {
     int lb, L;
-    Grid g[kMaxLevels + 1];
+    int used;   // LDS elements the levels occupy
+    BottomLevel lv[kMaxLevels + 1];
     const T* k1[kMaxLevels + 1];
     const T* k2[kMaxLevels + 1];
     const T* rin;
@@ -1283,16 +1307,7 @@ struct BottomArgs {
 constexpr int kBottomThreads = 512;
 constexpr int kBottomLds = 3072;   // elements: >= 2 * sum of the bottom levels' padded cells
 static_assert(kBottomMaxCells <= kBottomThreads, "one cell of each bottom level per thread");
-
-// The bottom levels live in LDS with a one-cell zero border, so that every
-// CConv tap is a fixed offset with no bounds test.
-__host__ __device__ inline int padded_cells(Grid g) { return (g.nx + 2) * (g.ny + 2) * (g.nz + 2); }
-
-__device__ __forceinline__ int padded_index(Grid g, int z, int y, int x) {
-    return ((z + 1) * (g.ny + 2) + (y + 1)) * (g.nx + 2) + (x + 1);
-}
-
-
+static_assert(kBottomThreads <= 512 && kBottomMaxCells <= 512, "cell splitting by div_magic");
 
 // A load through a pointer that is known to address device memory: pointers
 // read from a kernel-argument array are generic, and a generic (flat) load
@@ -1302,28 +1317,26 @@ __device__ __forceinline__ T ld_global(const T* p) {
     return *(const __attribute__((address_space(1))) T*)p;   // address-space cast (C-style only)
 }
 
-// One output of a stored-kernel CConv at cell p = (z, y, x) of grid g whose
-// input v sits in LDS (zero outside the grid).
-// One output of a stored-kernel CConv at padded index c of grid g (input v
-// in the padded layout: its border is zero, the CConv's zero padding).
+// One output of a stored-kernel CConv at padded index c of a level with
+// padded strides (sy, sz) (input v in the padded layout: its border is zero,
+// the CConv's zero padding).
 template <class T>
-__device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, Grid g, int c) {
-    const int sy = g.nx + 2, sz = (g.ny + 2) * sy;
+__device__ __forceinline__ T bottom_cconv(const T (&kv)[kTaps], const T* v, int sy, int sz, int c) {
     T acc = T(0);
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) acc = fma(kv[t], v[c + (t / 9 - 1) * sz + ((t / 3) % 3 - 1) * sy + (t % 3 - 1)], acc);
     return acc;
 }
 
-// Interp(xc) at fine cell (z, y, x) from the coarse grid gc in the padded
+// Interp(xc) at fine cell (z, y, x) from the coarse level vc in the padded
 // layout (coarse coordinates clamped: the interpolation's edge rule).
 template <class T>
-__device__ __forceinline__ T bottom_interp(const T* xc, Grid gc, int z, int y, int x) {
+__device__ __forceinline__ T bottom_interp(const T* xc, const BottomLevel& vc, int z, int y, int x) {
     int jx, jxn, jy, jyn, jz, jzn;
-    up_axis(x, gc.nx, jx, jxn);
-    up_axis(y, gc.ny, jy, jyn);
-    up_axis(z, gc.nz, jz, jzn);
-    auto at = [&](int zz, int yy, int xx) { return xc[padded_index(gc, zz, yy, xx)]; };
+    up_axis(x, vc.g.nx, jx, jxn);
+    up_axis(y, vc.g.ny, jy, jyn);
+    up_axis(z, vc.g.nz, jz, jzn);
+    auto at = [&](int zz, int yy, int xx) { return xc[(zz + 1) * vc.sz + (yy + 1) * vc.sy + xx + 1]; };
     const T a = T(0.75), b = T(0.25);
     const T p00 = a * at(jz, jy, jx) + b * at(jz, jy, jxn);
     const T p01 = a * at(jz, jyn, jx) + b * at(jz, jyn, jxn);
@@ -1336,23 +1349,17 @@ __device__ __forceinline__ T bottom_interp(const T* xc, Grid gc, int z, int y, i
 // kBottomThreads cells): every global load they need (r^lb and their stored
 // kernels) is issued at the start, so the sweep waits for one memory
 // latency instead of one per level.  Levels past lb + 1 (a handful of
-// cells) load their kernels where they are used.
+// cells) load their kernels where they are used.  The result of level l
+// (x1^l, then x^l once the up sweep has combined it in place) stays in the
+// level's x1 slot; the r slot holds r^l on the way down and Interp(x^(l+1))
+// on the way up.
 template <class T>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, State* st) {
     const int done = st->done;   // tested once the loads below are out
     __shared__ T buf[kBottomLds];
-    const int lb = a.lb, p = threadIdx.x;
-    // level l's two padded LDS slots, r^l (then x^l, the up sweep output) and
-    // x1^l, follow those of the finer bottom levels; addressed from buf
-    // directly (a table of pointers would make them generic pointers)
-    auto slot = [&](int l) {
-        int off = 0;
-        for (int m = lb; m < l; ++m) off += 2 * padded_cells(a.g[m]);
-        return off;
-    };
-    auto rb = [&](int l) { return buf + slot(l); };
-    auto x1 = [&](int l) { return buf + slot(l) + padded_cells(a.g[l]); };
-    const int n0 = (int)ncells(a.g[lb]), n1 = lb < a.L ? (int)ncells(a.g[lb + 1]) : 1;
+    const int lb = a.lb, L = a.L, p = threadIdx.x;
+    const BottomLevel v0 = a.lv[lb];
+    const int n0 = v0.n, n1 = lb < L ? a.lv[lb + 1].n : 1;
     const int q0 = min(p, n0 - 1), q1 = min(p, n1 - 1);   // clamped: every load is in bounds
     T r0 = ld_global(a.rin + q0);
     // the combination weights of level lb (set up before the solve)
@@ -1360,7 +1367,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
     T k1_0[kTaps], k2_0[kTaps], k1_1[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) k1_0[t] = ld_global(a.k1[lb] + (size_t)t * n0 + q0);
-    if (lb < a.L) {
+    if (lb < L) {
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) k2_0[t] = ld_global(a.k2[lb] + (size_t)t * n0 + q0);
 #pragma unroll
@@ -1380,88 +1387,76 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
         if (done_s) return;
     }
     // zero borders: clear the whole buffer, then fill the interiors
-    const int used = slot(a.L + 1);
-    for (int i = p; i < used; i += kBottomThreads) buf[i] = T(0);
-    __syncthreads();
+    for (int i = p; i < a.used; i += kBottomThreads) buf[i] = T(0);
     // cell p of a level (at most one per thread) and its padded index
-    auto cell = [&](Grid g, int& z, int& y, int& x) {
-        x = p % g.nx;
-        y = (p / g.nx) % g.ny;
-        z = p / (g.nx * g.ny);
-        return padded_index(g, z, y, x);
+    auto cell = [&](const BottomLevel& v, int& z, int& y, int& x) {
+        const int t = (int)(__umul24((uint32_t)p, v.mx) >> kDivShift);   // p / nx
+        z = (int)(__umul24((uint32_t)p, v.mxy) >> kDivShift);            // p / (nx ny)
+        x = p - t * v.g.nx;
+        y = t - z * v.g.ny;
+        return (z + 1) * v.sz + (y + 1) * v.sy + x + 1;
     };
-    {
-        int z, y, x;
-        const int c = cell(a.g[lb], z, y, x);
-        if (p < n0) rb(lb)[c] = r0;
-    }
+    int z0, y0, x0;
+    const int c0 = cell(v0, z0, y0, x0);
     __syncthreads();
-    for (int l = lb; l <= a.L; ++l) {       // down sweep and coarsest level
-        const Grid g = a.g[l];
-        const int nl = (int)ncells(g);
-        if (p < nl) {
-            int z, y, x;
-            const int c = cell(g, z, y, x);
-            if (l <= lb + 1) {
-                x1(l)[c] = bottom_cconv(l == lb ? k1_0 : k1_1, rb(l), g, c);
+    if (p < n0) buf[v0.r + c0] = r0;
+    __syncthreads();
+    // down sweep and coarsest level
+    if (p < n0) buf[v0.x1 + c0] = bottom_cconv(k1_0, buf + v0.r, v0.sy, v0.sz, c0);
+    __syncthreads();
+    for (int l = lb; l < L; ++l) {
+        const BottomLevel f = a.lv[l], v = a.lv[l + 1];
+        int z, y, x;
+        const int c = cell(v, z, y, x);
+        if (p < v.n) {   // Pool(x1^l)
+            const T* s = buf + f.x1 + (2 * z + 1) * f.sz + (2 * y + 1) * f.sy + 2 * x + 1;
+            T sum = T(0);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sum += s[(k >> 2) * f.sz + ((k >> 1) & 1) * f.sy + (k & 1)];
+            buf[v.r + c] = sum * T(0.125);
+        }
+        __syncthreads();
+        if (p < v.n) {
+            T acc;
+            if (l == lb) {
+                acc = bottom_cconv(k1_1, buf + v.r, v.sy, v.sz, c);
             } else {
                 T kv[kTaps];
 #pragma unroll
-                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k1[l] + (size_t)t * nl + p);
-                x1(l)[c] = bottom_cconv(kv, rb(l), g, c);
+                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k1[l + 1] + (size_t)t * v.n + p);
+                acc = bottom_cconv(kv, buf + v.r, v.sy, v.sz, c);
             }
+            buf[v.x1 + c] = acc;
         }
         __syncthreads();
-        if (l < a.L) {
-            const Grid gc = coarser(g);
-            if (p < (int)ncells(gc)) {
-                int z, y, x;
-                const int c = cell(gc, z, y, x);
-                const T* f = x1(l);
-                T s = T(0);
-                for (int k = 0; k < 8; ++k) s += f[padded_index(g, 2 * z + (k >> 2), 2 * y + ((k >> 1) & 1), 2 * x + (k & 1))];
-                rb(l + 1)[c] = s * T(0.125);
-            }
-            __syncthreads();
-        }
     }
     // up sweep: x^L = x1^L.  Interp(x^(l+1)) is formed once per level into the
     // level's r slot (its down input is no longer needed; the border stays
-    // zero), then CConv_2 gathers from it.
-    const T* xc = x1(a.L);
-    for (int l = a.L - 1; l >= lb; --l) {
-        const Grid g = a.g[l], gc = a.g[l + 1];
-        const int nl = (int)ncells(g);
+    // zero), then CConv_2 gathers from it and the combination overwrites
+    // x1^l, which only this thread reads, with x^l.
+    for (int l = L - 1; l >= lb; --l) {
+        const BottomLevel v = a.lv[l], vc = a.lv[l + 1];
         const T c1 = l == lb ? c1_0 : (T)st->c1[l - 1], c2 = l == lb ? c2_0 : (T)st->c2[l - 1];
-        T* up = rb(l);
-        int z = 0, y = 0, x = 0, c = 0;
-        if (p < nl) {
-            c = cell(g, z, y, x);
-            up[c] = bottom_interp<T>(xc, gc, z, y, x);
-        }
+        int z, y, x;
+        const int c = cell(v, z, y, x);
+        if (p < v.n) buf[v.r + c] = bottom_interp<T>(buf + vc.x1, vc, z, y, x);
         __syncthreads();
-        T out = T(0);
-        if (p < nl) {
+        if (p < v.n) {
             T acc;
             if (l == lb) {
-                acc = bottom_cconv(k2_0, up, g, c);
+                acc = bottom_cconv(k2_0, buf + v.r, v.sy, v.sz, c);
             } else {
                 T kv[kTaps];
 #pragma unroll
-                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k2[l] + (size_t)t * nl + p);
-                acc = bottom_cconv(kv, up, g, c);
+                for (int t = 0; t < kTaps; ++t) kv[t] = ld_global(a.k2[l] + (size_t)t * v.n + p);
+                acc = bottom_cconv(kv, buf + v.r, v.sy, v.sz, c);
             }
-            out = c1 * x1(l)[c] + c2 * acc;
+            T* xo = buf + v.x1 + c;
+            *xo = c1 * *xo + c2 * acc;
         }
-        __syncthreads();   // every gather from up is done before it is overwritten
-        if (p < nl) up[c] = out;
-        __syncthreads();
-        xc = rb(l);
+        if (l > lb) __syncthreads();   // level lb's cells are read back only by the thread that wrote them
     }
-    if (p < n0) {   // x^lb (x1^L itself when the bottom holds only the coarsest level)
-        int z, y, x;
-        a.xout[p] = xc[cell(a.g[lb], z, y, x)];
-    }
+    if (p < n0) a.xout[p] = buf[v0.x1 + c0];   // x^lb (x1^L itself when the bottom holds only the coarsest level)
 }
 
 // ---------------------------------------------------------------------------
