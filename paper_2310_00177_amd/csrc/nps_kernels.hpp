@@ -757,22 +757,40 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ partials
     }
 }
 
+// The state the Dots stage reads (sl: ring slots of d_(k-1), d_(k-2), ...),
+// gathered in one go so that its loads can go out early.
+struct DotsIn {
+    int method, nprev;
+    double dAd[kMaxOrtho];
+    double rho_prev;
+};
+
+__device__ __forceinline__ DotsIn dots_in(const State* st, const int (&sl)[kMaxOrtho]) {
+    DotsIn d;
+    d.method = st->method;
+    d.nprev = st->nprev;
+#pragma unroll
+    for (int j = 0; j < kMaxOrtho; ++j) d.dAd[j] = st->dAd[sl[j]];
+    d.rho_prev = st->rho_prev;
+    return d;
+}
+
 // The Dots stage: the coefficients beta_j of the direction update from the
 // summed dots v (and, for the PCG forms, rho = r . d^), formed without
-// writing the state (sl: ring slots of d_(k-1), d_(k-2), ...).
-__device__ __forceinline__ void dots_betas(const State* st, const double* v, const int (&sl)[kMaxOrtho],
-                                           double (&beta)[kMaxOrtho], double& rho) {
+// writing the state.
+__device__ __forceinline__ void dots_betas(const DotsIn& in, const double* v, double (&beta)[kMaxOrtho], double& rho) {
     rho = 0.0;
-    if (st->method == 0) {
-        for (int j = 0; j < kMaxOrtho; ++j) beta[j] = j < st->nprev ? v[j] / st->dAd[sl[j]] : 0.0;
+    if (in.method == 0) {
+#pragma unroll
+        for (int j = 0; j < kMaxOrtho; ++j) beta[j] = j < in.nprev ? v[j] / in.dAd[j] : 0.0;
     } else {
         // With s = P(r) = ||r|| d^ and directions kept scaled by 1/||r||,
         // d^_k + c d^_(k-1) is parallel to s_k + beta d_(k-1) for
         // c = beta ||r_(k-1)|| / ||r_k||: PCG c = rho_k / rho_(k-1),
         // flexible PCG c = (rho_k - d^_k . r_(k-1)) / rho_(k-1), rho = r . d^.
         rho = v[0];
-        const double num = st->method == 1 ? rho : rho - v[1];
-        beta[0] = st->nprev > 0 ? -num / st->rho_prev : 0.0;
+        const double num = in.method == 1 ? rho : rho - v[1];
+        beta[0] = in.nprev > 0 ? -num / in.rho_prev : 0.0;
         for (int j = 1; j < kMaxOrtho; ++j) beta[j] = 0.0;
     }
 }
@@ -854,7 +872,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
     } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
         const int sl[kMaxOrtho] = {i0, i1, i2, i3};
         double beta[kMaxOrtho], rho;
-        dots_betas(st, v, sl, beta, rho);
+        dots_betas(dots_in(st, sl), v, beta, rho);
         for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
         if (st->method != 0) st->rho = rho;
     } else if constexpr (STAGE == kStageLoss) {     // training loss: ||b - A y||^2
@@ -1509,31 +1527,15 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
                                                   const T* __restrict__ r, T* __restrict__ dout, T* __restrict__ adout,
                                                   State* st, const double* __restrict__ dots, int dnparts, int sl0,
                                                   int sl1, int sl2, int sl3, double* __restrict__ partials) {
-    if (st->done) return;
     __shared__ uint32_t lab_s[2][kPlaneP];
     __shared__ T d_s[2][kPlaneP];
     __shared__ double beta_s[kMaxOrtho];
+    const int done = st->done;   // tested once the first loads are out
     const int nprev = st->nprev;
+    const int sl[kMaxOrtho] = {sl0, sl1, sl2, sl3};
+    const DotsIn din = dots_in(st, sl);
+    const int ndots = st->ndots;
     T bj[kMaxOrtho] = {T(0), T(0), T(0), T(0)};
-    if (dnparts > 0) {   // the Dots stage
-        double dv[kMaxOrtho];
-        sum_partials<kMaxOrtho, kBlock>(dots, dnparts, st->ndots, dv);
-        if (threadIdx.x == 0) {
-            const int sl[kMaxOrtho] = {sl0, sl1, sl2, sl3};
-            double beta[kMaxOrtho], rho;
-            dots_betas(st, dv, sl, beta, rho);
-#pragma unroll
-            for (int j = 0; j < kMaxOrtho; ++j) beta_s[j] = beta[j];
-            if (blockIdx.x == 0) {
-#pragma unroll
-                for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
-                if (st->method != 0) st->rho = rho;
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int j = 0; j < kMaxOrtho; ++j) bj[j] = (T)beta_s[j];
-    }
     const T* pp[kMaxOrtho] = {p0, p1, p2, p3};
     const Columns cl = columns_of(g);
     const int lx = threadIdx.x % PX, ly = threadIdx.x / PX;
@@ -1563,6 +1565,7 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * e.p[j] : dv;
         return dv;
     };
+    bool first = true;
     for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
         const int w = sp.t0;
         const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
@@ -1571,6 +1574,34 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         const bool col = xx < g.nx && yy < g.ny;
         const LD below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
         auto pre = plane(x0, y0, z0);
+        if (first) {
+            __asm__ volatile("" ::: "memory");   // the loads stay above the test
+            if (done) return;
+            first = false;
+            if (dnparts > 0) {   // the Dots stage, its loads behind the first plane's
+                // the up kernel forms ndots <= max(NO, 2) dots (NPSDO: nprev
+                // <= n_ortho; the PCG forms: 1 or 2)
+                constexpr int DW = NO > 2 ? NO : 2;
+                double dw[DW], dv[kMaxOrtho] = {0.0, 0.0, 0.0, 0.0};
+                sum_partials<DW, kBlock>(dots, dnparts, ndots, dw);
+                if (threadIdx.x == 0) {
+#pragma unroll
+                    for (int j = 0; j < DW; ++j) dv[j] = dw[j];
+                    double beta[kMaxOrtho], rho;
+                    dots_betas(din, dv, beta, rho);
+#pragma unroll
+                    for (int j = 0; j < kMaxOrtho; ++j) beta_s[j] = beta[j];
+                    if (blockIdx.x == 0) {
+#pragma unroll
+                        for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
+                        if (din.method != 0) st->rho = rho;
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int j = 0; j < kMaxOrtho; ++j) bj[j] = (T)beta_s[j];
+            }
+        }
         T dm = direction(below);   // own column, plane s - 2
         uint32_t lm = below.l;
         T rv = T(0);               // r of plane s - 1
