@@ -352,14 +352,36 @@ __device__ __forceinline__ T cconv_pure(const T* r_s, int base, const CConvW<T>*
 // Stored kernels: K[t][cell] formed at setup.  The 27 loads are issued
 // together before the multiply-adds (one memory latency, not 27).
 template <class T>
-__device__ __forceinline__ T cconv_stored(const T* r_s, int base, const T* __restrict__ kst, size_t n, size_t idx) {
-    T kv[kTaps];
-#pragma unroll
-    for (int t = 0; t < kTaps; ++t) kv[t] = kst[(size_t)t * n + idx];
+__device__ __forceinline__ T cconv_stored(const T* r_s, int base, const T (&kv)[kTaps]) {
     T acc = T(0);
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) acc = fma(kv[t], r_s[base + halo_off(t)], acc);
     return acc;
+}
+
+// The stored kernel of the thread's cell, loaded at the start of a tile so
+// that its latency overlaps the staging instead of following it.  Done by
+// the float kernels of levels >= 2 only: 27 doubles do not stay in
+// registers beside the staging, nor 27 floats beside the level-1 staging
+// (the others load it where the CConv needs it).
+template <class T, int KM, bool COARSE>
+constexpr bool kpre_on = KM == kStored && COARSE && sizeof(T) == 4;
+
+template <class T, bool ON>
+struct KPre {};
+template <class T>
+struct KPre<T, true> {
+    T kv[kTaps];
+};
+
+template <class T, bool ON>
+__device__ __forceinline__ KPre<T, ON> k_preload(const T* __restrict__ kst, size_t n, size_t idx) {
+    KPre<T, ON> k;
+    if constexpr (ON) {
+#pragma unroll
+        for (int t = 0; t < kTaps; ++t) k.kv[t] = kst[(size_t)t * n + idx];
+    }
+    return k;
 }
 
 __device__ __forceinline__ int halo_off_rt(int o) {   // runtime version of halo_off
@@ -487,14 +509,24 @@ __device__ __forceinline__ float cconv_mfma(const uint32_t* feat_s, const float*
 }
 
 // One CConv output of the thread's cell (lx, ly, lz) for a wave-uniform mode.
-template <class T, int KM, bool L1>
+// kp: the preloaded stored kernel (PRE), else loaded here from kst.
+template <class T, int KM, bool L1, bool PRE>
 __device__ __forceinline__ T cconv_any(int mode, bool active, const uint32_t* img_s, const uint32_t* feat_s,
                                        const T* r_s, int base, const CConvW<T>* __restrict__ w,
-                                       const MfmaCtx<KM>& mc, const T* __restrict__ kst, size_t n, size_t idx) {
+                                       const MfmaCtx<KM>& mc, const T* __restrict__ kst, size_t n, size_t idx,
+                                       const KPre<T, PRE>& kp) {
     if (mode == -3) return T(0);
     if (mode >= 0) return active ? cconv_pure<T>(r_s, base, w, mode) : T(0);
     if constexpr (KM == kStored) {
-        return active ? cconv_stored<T>(r_s, base, kst, n, idx) : T(0);
+        if (!active) return T(0);
+        if constexpr (PRE) {
+            return cconv_stored<T>(r_s, base, kp.kv);
+        } else {
+            T kv[kTaps];
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) kv[t] = kst[(size_t)t * n + idx];
+            return cconv_stored<T>(r_s, base, kv);
+        }
     } else if constexpr (KM == kVector) {
         return active ? cconv_vector<T, L1>(img_s, r_s, base, w) : T(0);
     } else {
@@ -959,6 +991,9 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
         __syncthreads();
         put_batch(pre, [&](int i, RL<T> e) {
             r_s[i] = e.l == kFluid ? e.r : T(0);
@@ -967,11 +1002,9 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(3) void k_down_l1(
         });
         prefetch();
         __syncthreads();
-        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
-        const bool active = in_grid(g, zz, yy, xx);
-        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
         const int mode = wave_mode<true>(wmode, wm_e, active, img_s, base, 1u, true, false);
-        const T out = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
+        const T out = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx,
+                                             KPre<T, false>{});
         if (active) x1[idx] = out;
         out_s[threadIdx.x] = active ? out : T(0);
         __syncthreads();
@@ -1010,6 +1043,10 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
+        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
+        const bool active = in_grid(g, zz, yy, xx);
+        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const auto kp = k_preload<T, kpre_on<T, KM, true>>(kst, n, idx);
         __syncthreads();
         put_batch(pre, [&](int i, CR<T> e) {
             img_s[i] = e.c;
@@ -1018,11 +1055,8 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_do
         });
         prefetch();
         __syncthreads();
-        const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
-        const bool active = in_grid(g, zz, yy, xx);
-        const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
         const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, wm_e, active, img_s, base, full, false, false);
-        const T out = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
+        const T out = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx, kp);
         if (active) x1[idx] = out;
         if (POOL) {
             out_s[threadIdx.x] = active ? out : T(0);
@@ -1200,18 +1234,19 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
-        __syncthreads();
-        put_image_interp<false, KM, T>(pre, img_s, feat_s, c_s);
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        const auto kp = k_preload<T, kpre_on<T, KM, true>>(kst, n, idx);
+        __syncthreads();
+        put_image_interp<false, KM, T>(pre, img_s, feat_s, c_s);
         const T x1v = x1[idx];
         prefetch();
         __syncthreads();
         interp_tile<T>(r_s, c_s, g, o, isl);
         __syncthreads();
         const int mode = KM == kStored ? -1 : wave_mode<false>(wmode, wm_e, active, img_s, base, full, false, false);
-        const T x2 = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
+        const T x2 = cconv_any<T, KM, false>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx, kp);
         if (active) xout[idx] = c1 * x1v + c2 * x2;
         if (active && x2out) x2out[idx] = x2;
     }, st);
@@ -1247,11 +1282,11 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
     const bool ran = tile_pipeline(tl.count(), load, [&](int tile, const auto& pre, auto prefetch) {
         const TileOrigin o = tile_origin(tile, tl);
         const int wm_e = wave_mode_entry(wmode, tile, lz);
-        __syncthreads();
-        put_image_interp<true, KM, T>(pre, img_s, feat_s, c_s);
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         const bool active = in_grid(g, zz, yy, xx);
         const size_t idx = active ? cell_index(g, zz, yy, xx) : 0;
+        __syncthreads();
+        put_image_interp<true, KM, T>(pre, img_s, feat_s, c_s);
         // per-cell operands, issued before the next tile's loads (an unused
         // A d_i slot reads x1 instead: always a valid address)
         const T x1v = x1[idx];
@@ -1263,7 +1298,8 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(waves_floor(KM)) void k_up
         interp_tile<T>(r_s, c_s, g, o, isl);
         __syncthreads();
         const int mode = wave_mode<true>(wmode, wm_e, active, img_s, base, 1u, false, true);
-        const T x2 = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx);
+        const T x2 = cconv_any<T, KM, true>(mode, active, img_s, feat_s, r_s, base, w, mc, kst, n, idx,
+                                            KPre<T, false>{});
         if (active) {
             T out = T(0);
             if (img_s[base] == (uint32_t)kFluid) out = (c1 * x1v + c2 * x2) * scale;
