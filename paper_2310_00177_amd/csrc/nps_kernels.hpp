@@ -841,25 +841,78 @@ __device__ __forceinline__ void host_flags(HostFlags* hf, int iter, int done) {
 // search; PCG forms: alpha = r . s / d . A d), or a breakdown when d . A d is
 // not positive or a dot is not finite.  step_alpha forms it without writing
 // the state; step_update also records it (i0: ring slot of the direction).
-__device__ __forceinline__ bool step_alpha(const State* st, double dAd, double rd, double& alpha) {
+struct StepIn {
+    int method;
+    double rho;
+};
+
+__device__ __forceinline__ StepIn step_in(const State* st) { return StepIn{st->method, st->rho}; }
+
+__device__ __forceinline__ bool step_alpha(const StepIn& in, double dAd, double rd, double& alpha) {
     if (!(dAd > 0.0) || !isfinite(dAd) || !isfinite(rd)) return false;
-    alpha = (st->method == 0 ? rd : st->rho) / dAd;
+    alpha = (in.method == 0 ? rd : in.rho) / dAd;
     return true;
 }
 
-__device__ __forceinline__ void step_update(State* st, int i0, double dAd, double rd, HostFlags* hf) {
+__device__ __forceinline__ void step_update(State* st, const StepIn& in, int i0, double dAd, double rd,
+                                            HostFlags* hf) {
     double alpha;
     st->dAd[i0] = dAd;
     st->rd = rd;
-    if (!step_alpha(st, dAd, rd, alpha)) {
+    if (!step_alpha(in, dAd, rd, alpha)) {
         st->done = 1;
         st->status = -6;   // NPS_EBREAKDOWN
         if (hf) host_flags(hf, st->iter, 1);
     } else {
         st->alpha = alpha;
-        st->rho_prev = st->rho;
+        st->rho_prev = in.rho;
         st->pending = 1;
     }
+}
+
+// The state the Residual stage reads, gathered in one go so that its loads
+// can go out early.
+struct ResidualIn {
+    int iter, pending, xcur, n_ortho, method, fixed, max_iter;
+    double tol2bb;
+};
+
+__device__ __forceinline__ ResidualIn residual_in(const State* st) {
+    return ResidualIn{st->iter, st->pending, st->xcur, st->n_ortho, st->method, st->fixed, st->max_iter, st->tol2bb};
+}
+
+// The Residual stage from rr = ||b - A x_k||^2 of the iterate down_l1 just
+// formed: the iteration count, 1/||r||, the dot count and the convergence
+// test; returns the stop flag.
+__device__ __forceinline__ int residual_stage(State* st, const ResidualIn& in, double rr, HostFlags* hf) {
+    const int iter = in.iter + (in.pending ? 1 : 0);
+    st->iter = iter;
+    st->xcur = in.xcur ^ 1;   // the residual kernel wrote the other solution buffer
+    st->pending = 0;
+    st->rr = rr;
+    st->scale = rr > 0.0 ? 1.0 / sqrt(rr) : 0.0;
+    const int nprev = min(iter, in.n_ortho);
+    st->nprev = nprev;
+    // NPSDO: d^ . A d_i per previous direction; PCG: r . d^; flexible PCG
+    // also d^ . r_(k-1)
+    st->ndots = in.method == 0 ? nprev : in.method == 1 ? 1 : 2;
+    int done = 0, status = 0;
+    if (!isfinite(rr)) {
+        done = 1;
+        status = -6;   // NPS_EBREAKDOWN
+    } else if (!in.fixed && rr < in.tol2bb) {
+        done = 1;
+        status = 0;
+    } else if (iter >= in.max_iter) {
+        done = 1;
+        status = in.fixed ? 0 : 1;   // NPS_OK / NPS_NOT_CONVERGED
+    }
+    if (done) {
+        st->done = 1;
+        st->status = status;
+    }
+    if (hf) host_flags(hf, iter, done);
+    return done;
 }
 
 // The state update of one stage from its summed partials v (one thread).
@@ -879,28 +932,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
         st->c1[i0] = d0 + v[0] / d2;
         st->c2[i0] = d1 + v[1] / d2;
     } else if constexpr (STAGE == kStageResidual) { // ||b - A x_k||^2 of the iterate down_l1 just formed
-        const double rr = v[0];
-        const int iter = st->iter + (st->pending ? 1 : 0);
-        st->iter = iter;
-        st->xcur ^= 1;          // the residual kernel wrote the other solution buffer
-        st->pending = 0;
-        st->rr = rr;
-        st->scale = rr > 0.0 ? 1.0 / sqrt(rr) : 0.0;
-        st->nprev = min(iter, st->n_ortho);
-        // NPSDO: d^ . A d_i per previous direction; PCG: r . d^; flexible PCG
-        // also d^ . r_(k-1)
-        st->ndots = st->method == 0 ? st->nprev : st->method == 1 ? 1 : 2;
-        if (!isfinite(rr)) {
-            st->done = 1;
-            st->status = -6;   // NPS_EBREAKDOWN
-        } else if (!st->fixed && rr < st->tol2bb) {
-            st->done = 1;
-            st->status = 0;
-        } else if (iter >= st->max_iter) {
-            st->done = 1;
-            st->status = st->fixed ? 0 : 1;   // NPS_OK / NPS_NOT_CONVERGED
-        }
-        if (hf) host_flags(hf, iter, st->done);
+        residual_stage(st, residual_in(st), v[0], hf);
     } else if constexpr (STAGE == kStageDots) {     // i0..i3: ring slots of d_(k-1), d_(k-2), ...
         const int sl[kMaxOrtho] = {i0, i1, i2, i3};
         double beta[kMaxOrtho], rho;
@@ -910,7 +942,7 @@ __device__ __forceinline__ void control_update(State* st, const double* v, int i
     } else if constexpr (STAGE == kStageLoss) {     // training loss: ||b - A y||^2
         st->rr = v[0];
     } else if constexpr (STAGE == kStageStep) {     // i0: ring slot of the new direction
-        step_update(st, i0, v[0], v[1], hf);
+        step_update(st, step_in(st), i0, v[0], v[1], hf);
     }
 }
 
@@ -1410,6 +1442,7 @@ __device__ __forceinline__ T bottom_interp(const T* xc, const BottomLevel& vc, i
 template <class T>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, State* st) {
     const int done = st->done;   // tested once the loads below are out
+    const ResidualIn rin = residual_in(st);   // read by the Residual stage below
     __shared__ T buf[kBottomLds];
     const int lb = a.lb, L = a.L, p = threadIdx.x;
     const BottomLevel v0 = a.lv[lb];
@@ -1433,10 +1466,7 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
         __shared__ int done_s;
         double v[1];
         sum_partials<1, kBottomThreads>(a.res_partials, a.res_nparts, 1, v);
-        if (p == 0) {
-            control_update<kStageResidual>(st, v, 0, 0, 0, 0, 0.0, 0.0, 0.0, a.hf);
-            done_s = st->done;
-        }
+        if (p == 0) done_s = residual_stage(st, rin, v[0], a.hf);
         __syncthreads();
         if (done_s) return;
     }
@@ -1709,6 +1739,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
     __shared__ double alpha_s;
     __shared__ int ok_s;
     const int done = st->done;   // tested once the first loads are out
+    const StepIn sin = step_in(st);   // read by the Step stage below
     const bool pend = snp > 0;
     X alpha = X(0);
     const Columns cl = columns_of(g);
@@ -1743,9 +1774,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
                 sum_partials<2, kBlock>(steps, snp, 2, v);
                 if (threadIdx.x == 0) {
                     double a = 0.0;
-                    ok_s = step_alpha(st, v[0], v[1], a);
+                    ok_s = step_alpha(sin, v[0], v[1], a);
                     alpha_s = a;
-                    if (blockIdx.x == 0) step_update(st, slot, v[0], v[1], hf);
+                    if (blockIdx.x == 0) step_update(st, sin, slot, v[0], v[1], hf);
                 }
                 __syncthreads();
                 if (!ok_s) return;
