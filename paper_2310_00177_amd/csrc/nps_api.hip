@@ -500,14 +500,24 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     for (int l = 1; l <= L; ++l) {
         if (plan.km[l] != kStored) continue;
         const Grid g = level_grid(d, l);
-        const int grid = elem_grid((size_t)kTaps * ncells(g));   // one thread per (tap, cell)
+        // one thread per (tap, cell) on levels the solve stores; one per cell
+        // (its window read once for all taps) on larger ones (training)
+        const bool per_cell = ncells(g) > (size_t)kStoreMaxCells;
+        const int grid = elem_grid((per_cell ? 1 : (size_t)kTaps) * ncells(g));
         for (int which = 0; which < (l < L ? 2 : 1); ++which) {
             T* out = mptr<T>(ws, which == 0 ? lay.k1[l] : lay.k2[l]);
             const CConvW<double>* w = cconv_block<double>(net, which == 0 ? block_down(l) : block_up(net, l));
-            if (l == 1)
-                NPS_TRY(launch("setup_kgen", (double)ncells(g), s, [&] { k_kgen_store<T, true><<<grid, kBlock, 0, s>>>(img(l), g, w, out); }));
-            else
-                NPS_TRY(launch("setup_kgen", (double)ncells(g), s, [&] { k_kgen_store<T, false><<<grid, kBlock, 0, s>>>(img(l), g, w, out); }));
+            auto go = [&](auto l1, auto tg) {
+                constexpr bool L1 = decltype(l1)::value;
+                constexpr int TG = decltype(tg)::value;
+                return launch("setup_kgen", (double)ncells(g), s, [&] {
+                    k_kgen_store<T, L1, TG><<<grid, kBlock, 0, s>>>(img(l), g, w, out);
+                });
+            };
+            using one = std::integral_constant<int, 1>;
+            using all = std::integral_constant<int, kTaps>;
+            if (l == 1) NPS_TRY(per_cell ? go(std::true_type{}, all{}) : go(std::true_type{}, one{}));
+            else NPS_TRY(per_cell ? go(std::false_type{}, all{}) : go(std::false_type{}, one{}));
         }
     }
     return NPS_OK;

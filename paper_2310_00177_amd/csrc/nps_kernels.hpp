@@ -676,19 +676,28 @@ __global__ __launch_bounds__(kBlock) void k_aff(const void* __restrict__ img, Gr
 }
 
 // K[t][cell] of one CConv block on one level, formed in double (setup).
-template <class T, bool L1>
+template <class T, bool L1, int TG>
 __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ img, Grid g,
                                                        const CConvW<double>* __restrict__ w, T* __restrict__ kst) {
-    // one thread per (tap t, cell p), i = t n + p: the taps of a block share
-    // their weights (uniform loads), the stores are contiguous; each tap sums
-    // its 27 window terms in the same order as a per-cell loop would
+    // one thread per (group j of TG taps, cell p), i = j n + p: the taps of a
+    // block share their weights (uniform loads), the stores are contiguous;
+    // each tap sums its 27 window terms in window order.  TG = 1 spreads a
+    // small level over many threads; TG = 27 reads each window once on a
+    // large one (27 taps per thread would re-read it 27 times)
+    static_assert(kTaps % TG == 0, "whole tap groups");
     const size_t n = ncells(g);
-    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < (size_t)kTaps * n; i += (size_t)gridDim.x * kBlock) {
-        const int t = (int)(i / n);
-        const size_t p = i - (size_t)t * n;
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < (size_t)(kTaps / TG) * n;
+         i += (size_t)gridDim.x * kBlock) {
+        const int t0 = (int)(i / n) * TG;
+        const size_t p = i - (size_t)(t0 / TG) * n;
         const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
-        double K = w->C[t];
+        double K[TG];
 #pragma unroll
+        for (int u = 0; u < TG; ++u) K[u] = w->C[t0 + u];
+        // the window loop is unrolled for one tap; with all 27 it stays a loop
+        // (27 x 27 unrolled terms would not fit the instruction cache)
+        constexpr int UO = TG == 1 ? kTaps : 1;
+#pragma unroll UO
         for (int o = 0; o < kTaps; ++o) {
             // solid padding (no fluid, no air) outside the grid: the cell itself is
             // read there and its weights zeroed, so the 27 reads are unconditional
@@ -699,9 +708,12 @@ __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ 
             uint32_t c0, c1;
             counts_of<L1>(v, c0, c1);
             const double m = in ? 1.0 : 0.0;
-            K += (w->D[o][t][0] * m) * (double)c0 + (w->D[o][t][1] * m) * (double)c1;
+#pragma unroll
+            for (int u = 0; u < TG; ++u)
+                K[u] += (w->D[o][t0 + u][0] * m) * (double)c0 + (w->D[o][t0 + u][1] * m) * (double)c1;
         }
-        kst[i] = (T)K;
+#pragma unroll
+        for (int u = 0; u < TG; ++u) kst[(size_t)(t0 + u) * n + p] = (T)K[u];
     }
 }
 
