@@ -1330,6 +1330,16 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
     return NPS_OK;
 }
 
+// The weight-gradient sums of one CConv block from nparts per-block rows:
+// chunk sums in place, then the final reduction into gW (and dc).
+int wgrad_reduce(double* wpart, int nparts, double scale, double* gW, double* dc, hipStream_t s) {
+    const dim3 cgrid((nparts + kWChunk - 1) / kWChunk, (kWPart + kBlock - 1) / kBlock);
+    NPS_TRY(launch("train_wgrad_chunks", 0, s, [&] { k_wgrad_chunks<<<cgrid, kBlock, 0, s>>>(wpart, nparts); }));
+    return launch("train_wgrad_reduce", 0, s, [&] {
+        k_wgrad_reduce<<<1, kBlock, 0, s>>>(wpart, nparts, scale, gW, gW + 27 * 81, dc);
+    });
+}
+
 template <class T>
 int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws,
                    const T* r, const T* gy, double* grad, hipStream_t s) {
@@ -1364,9 +1374,7 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
         const double scale = std::ldexp(1.0, -3 * (l - 1));
         double* gW = grad + off_c2(L, l);
         double* dcl = dc + 2 * (l - 1);
-        NPS_TRY(launch("train_wgrad_reduce", 0, s, [&] {
-            k_wgrad_reduce<<<1, kBlock, 0, s>>>(wpart, grid, scale, gW, gW + 27 * 81, dcl);
-        }));
+        NPS_TRY(wgrad_reduce(wpart, grid, scale, gW, dcl, s));
         const double* sp = cptr<double>(ws, tl.spart) + (size_t)(l - 1) * 3 * kTaps * kSumBlocks;
         double* ga = grad + off_aff(L, l);
         const double n27 = 27.0 * (double)ncells(g);
@@ -1396,9 +1404,7 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
             }));
         const double scale = std::ldexp(1.0, -3 * (l - 1));
         double* gW = grad + off_c1(l);
-        NPS_TRY(launch("train_wgrad_reduce", 0, s, [&] {
-            k_wgrad_reduce<<<1, kBlock, 0, s>>>(wpart, grid, scale, gW, gW + 27 * 81, nullptr);
-        }));
+        NPS_TRY(wgrad_reduce(wpart, grid, scale, gW, nullptr, s));
     }
     (void)st;
     return NPS_OK;

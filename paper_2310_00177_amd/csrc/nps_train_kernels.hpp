@@ -262,16 +262,49 @@ __global__ __launch_bounds__(kBlock) void k_bwd_interp(Grid gcoarse, const T* __
     }
 }
 
-// Sums the per-block partials of one CConv block's parameter sums (block
-// order) into the gradient blob: W[t][c][o] (c = fluid, air scaled by
-// 1/8^(l-1); solid from U_t), B[t] = U_t.  Also returns dL/dc1, dL/dc2 into dc.
+// The per-block partials of the parameter sums are reduced in two passes
+// of fixed order: k_wgrad_chunks sums each chunk of kWChunk consecutive rows
+// into the chunk's first row (in place: no other block reads that chunk),
+// then k_wgrad_reduce sums the first rows in chunk order.  One workgroup
+// summing every row itself had 12 MB to read per CConv block.
+constexpr int kWChunk = 32;
+
+__global__ __launch_bounds__(kBlock) void k_wgrad_chunks(double* __restrict__ part, int nparts) {
+    const int idx = blockIdx.y * kBlock + threadIdx.x;   // column
+    const int b0 = blockIdx.x * kWChunk, b1 = min(b0 + kWChunk, nparts);
+    if (idx >= kWPart) return;
+    constexpr int U = 8;
+    double s = 0.0;
+    for (int b = b0; b < b1; b += U) {
+        double t[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t[u] = b + u < b1 ? part[(size_t)(b + u) * kWPart + idx] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += t[u];
+    }
+    part[(size_t)b0 * kWPart + idx] = s;
+}
+
+// Sums the chunk sums (rows 0, kWChunk, 2 kWChunk, ... below nparts) of one
+// CConv block's parameter sums into the gradient blob: W[t][c][o] (c =
+// fluid, air scaled by 1/8^(l-1); solid from U_t), B[t] = U_t.  Also
+// returns dL/dc1, dL/dc2 into dc.
 __global__ __launch_bounds__(kBlock) void k_wgrad_reduce(const double* __restrict__ part, int nparts, double scale,
                                                          double* __restrict__ gW, double* __restrict__ gB,
                                                          double* __restrict__ dc) {
     __shared__ double sums[kWPart];
+    const int nchunks = (nparts + kWChunk - 1) / kWChunk;
     for (int idx = threadIdx.x; idx < kWPart; idx += kBlock) {
+        constexpr int U = 8;
         double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += part[(size_t)b * kWPart + idx];
+        for (int c = 0; c < nchunks; c += U) {
+            double t[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                t[u] = c + u < nchunks ? part[(size_t)(c + u) * kWChunk * kWPart + idx] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += t[u];
+        }
         sums[idx] = s;
     }
     __syncthreads();
