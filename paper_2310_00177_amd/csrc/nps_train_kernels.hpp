@@ -370,8 +370,17 @@ __global__ __launch_bounds__(kBlock) void k_image_sums(const void* __restrict__ 
 __global__ void k_aff_grad(const double* __restrict__ spart, int nparts, const double* __restrict__ dc, double n27,
                            double* __restrict__ gA1, double* __restrict__ gA2) {
     for (int i = threadIdx.x; i < 3 * kTaps; i += blockDim.x) {
+        // the partials in block order, U loads in flight per round trip
+        constexpr int U = 16;
         double s = 0.0;
-        for (int b = 0; b < nparts; ++b) s += spart[(size_t)b * 3 * kTaps + i];
+        for (int b0 = 0; b0 < nparts; b0 += U) {
+            double t[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) t[u] = b0 + u < nparts ? spart[(size_t)(b0 + u) * 3 * kTaps + i] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (b0 + u < nparts) s += t[u];
+        }
         gA1[i] += dc[0] * s / n27;   // Wbar[c][o] with i = c * 27 + o
         gA2[i] += dc[1] * s / n27;
     }
