@@ -49,7 +49,7 @@ class nps_kernel_stat(ctypes.Structure):
 
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2310_00177_amd.build`")
+    raise ImportError(f"{LIB_PATH} is not built; run `python paper_2310_00177_amd/build.py`")
 
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _sz, _int = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int

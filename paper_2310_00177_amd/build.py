@@ -1,6 +1,6 @@
 """Build the HIP library (libnps.so) for gfx950, in-tree.
 
-    python -m paper_2310_00177_amd.build        # or build() from Python
+    python paper_2310_00177_amd/build.py        # or build() from Python
 
 Every HIP source is compiled into one translation unit (nps_api.hip includes
 the kernels) with packed-FP32 instructions disabled.  The right-hand-side
