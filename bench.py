@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--max-iter", type=int, default=2000)
     ap.add_argument("--headline", default="mixed_bf16", choices=["mixed_bf16", "mixed_fp16", "fp32", "fp64"])
     ap.add_argument("--compare", default="fp32", help="second precision to time, or 'none'")
+    ap.add_argument("--compare2", default="mixed_fp16", help="third precision to time, or 'none'")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="end with known-size fill and negate kernels (1 GiB each) for the HBM counters")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -82,36 +83,34 @@ def parse():
     return ap.parse_args()
 
 
-# Algorithmic HBM bytes per cell of each kernel (compulsory traffic of the
-# method, labels-only operator reads), with s = bytes per vector element and
-# xs = bytes per solution element (8 in the mixed modes, where x is double):
-#   residual      x, d, b (8), labels -> x, r
-#                 (x + alpha d, r = b - A x)                   2 xs + 2 s + 9
-#   net_down_l1   r, labels -> x1, pooled r (CConv_1, pool)    (2 + 1/8) s + 1
-#   net_up_l1     x2 (1/8), labels, x1, n_prev Ad -> dhat      (2 + 1/8 + n_prev) s + 1
-#   ortho_matvec  dhat, n_prev d, r, labels -> d, Ad           (4 + n_prev) s + 1
-#   net_down / net_up (coarse levels): 4 B of packed counts instead of 1 B labels
-def alg_bytes_per_cell(kernel: str, s: int, xs: int = None, n_prev: int = 2) -> float | None:
-    xs = s if xs is None else xs
+# Algorithmic HBM bytes per fine cell and iteration: the method's compulsory
+# traffic with labels-only operator reads, per pass, with s = bytes per Krylov
+# element and a = bytes per network activation (s = 8, a = 8 in FP64; s = 4,
+# a = 4 in FP32; s = 4, a = 2 in the mixed modes):
+#   net-down l1 (CConv_1^1 + pool)        r, labels -> x1, r2         s + 1 + 1.125 a
+#   coarse levels 2..6, down + up         counts as 2 x u16           0.143 (4.25 a + 8)
+#   net-up l1 + the beta dots             x2, labels, x1, Ad_(k-1), Ad_(k-2) -> dhat
+#                                                                     3 s + 1.125 a + 1
+#   ortho + matvec + the alpha dots       dhat, d_(k-1), d_(k-2), Ad_(k-1), Ad_(k-2), r,
+#                                         labels -> d, Ad             8 s + 1
+#   update                                x, d, r, Ad -> x, r         6 s
+#   mixed modes: FP64 refinement          (8 + 8 + 1 + 4 + 4 + 8) / 20 ~ 1.7
+# The library's kernels map onto these passes one to one (`residual` is the
+# update, with the literal residual), except that the coarse levels run as
+# several launches.
+def alg_bytes_per_cell(kernel: str, s: int, a: int) -> float | None:
     table = {
-        "residual": 2 * xs + 2 * s + 9,
-        "net_down_l1": 2.125 * s + 1,
-        "net_up_l1": (2.125 + n_prev) * s + 1,
-        "ortho_matvec": (4 + n_prev) * s + 1,
-        "net_down": 2.125 * s + 4,
-        "net_up": 2.125 * s + 4,
-        "net_coarsest": 2 * s + 4,
+        "net_down_l1": s + 1 + 1.125 * a,
+        "net_up_l1": 3 * s + 1.125 * a + 1,
+        "ortho_matvec": 8 * s + 1,
+        "residual": 6 * s,
     }
     return table.get(kernel)
 
 
-def iteration_bytes_per_fine_cell(s: int, xs: int, n_prev: int = 2) -> float:
-    """All per-iteration kernels, coarse levels weighted by their 1/8^(l-1) share."""
-    coarse = sum(8.0 ** -(l - 1) for l in range(2, 7))
-    return (alg_bytes_per_cell("residual", s, xs) + alg_bytes_per_cell("net_down_l1", s, xs)
-            + alg_bytes_per_cell("net_up_l1", s, xs, n_prev)
-            + alg_bytes_per_cell("ortho_matvec", s, xs, n_prev)
-            + coarse * (alg_bytes_per_cell("net_down", s) + alg_bytes_per_cell("net_up", s)))
+def iteration_bytes_per_fine_cell(s: int, a: int, mixed: bool) -> float:
+    """All passes of one iteration (the sum above, ~83.5 B mixed, ~88 B FP32)."""
+    return 18 * s + (1.125 + 1.125 + 0.143 * 4.25) * a + 3 + 0.143 * 8 + (1.7 if mixed else 0.0)
 
 
 def cpu_baseline(labels, b, params, iters_sample):
@@ -375,6 +374,9 @@ def main():
     comp = None
     if args.compare and args.compare not in ("none", args.headline):
         comp, _, _ = run(args.compare, args.steps, args.warmup)
+    comp2 = None
+    if args.compare2 and args.compare2 not in ("none", args.headline, args.compare):
+        comp2, _, _ = run(args.compare2, args.steps, args.warmup)
 
     # solver variants on the same system (the paper's PCG-variant and n_ortho
     # comparisons): NPSDO with n_ortho 0..4 (0 = steepest descent), PCG, flexible PCG
@@ -391,7 +393,7 @@ def main():
     # profiled pass: per-kernel durations from HIP events on the launch stream
     prec = prec_of[args.headline]
     s_bytes = 8 if prec == nps.FP64 else 4
-    x_bytes = 4 if prec == nps.FP32 else 8
+    a_bytes = {nps.FP64: 8, nps.FP32: 4}.get(prec, 2)
     _lib.nps_profile_enable(1)
     prof_solves = max(2, min(args.steps, 5))
     t_iter_sum, its_sum = 0.0, 0
@@ -402,12 +404,12 @@ def main():
     _lib.nps_profile_enable(0)
     kstats = {s.name.decode(): (s.launches, s.total_ms, s.cells) for s in stats}
     per_iter_ms = sum(v[1] for k, v in kstats.items() if not k.startswith("setup") and k not in ("state_init", "finalize")) / max(its_sum, 1)
-    dom = max((k for k in kstats if alg_bytes_per_cell(k, s_bytes) is not None), key=lambda k: kstats[k][1])
+    dom = max((k for k in kstats if alg_bytes_per_cell(k, s_bytes, a_bytes) is not None), key=lambda k: kstats[k][1])
     launches, total_ms, cells = kstats[dom]
     avg_s = total_ms / launches * 1e-3
-    bytes_per_launch = alg_bytes_per_cell(dom, s_bytes, x_bytes) * cells / launches
+    bytes_per_launch = alg_bytes_per_cell(dom, s_bytes, a_bytes) * cells / launches
     achieved = bytes_per_launch / avg_s / 1e9
-    it_bytes = iteration_bytes_per_fine_cell(s_bytes, x_bytes) * lab.size
+    it_bytes = iteration_bytes_per_fine_cell(s_bytes, a_bytes, prec in (nps.MIXED_BF16, nps.MIXED_FP16)) * lab.size
     kernels = {k: {"launches": v[0], "avg_us": v[1] / v[0] * 1e3, "share": v[1] / sum(w[1] for w in kstats.values())}
                for k, v in kstats.items()}
     print("# kernels: " + ", ".join(f"{k} {v['avg_us']:.1f}us x{v['launches']} ({v['share'] * 100:.1f}%)"
@@ -449,6 +451,10 @@ def main():
             "p99_ms": comp["p99_ms"], "iterations": comp["iterations"],
             "rel_residual_true": comp["rel_residual_true"], "converged": comp["converged"],
             "speedup_headline_vs_compare": head["solves_per_s"] / comp["solves_per_s"]},
+        "compare2": None if comp2 is None else {
+            "precision": args.compare2, "value": comp2["solves_per_s"], "p50_ms": comp2["p50_ms"],
+            "p99_ms": comp2["p99_ms"], "iterations": comp2["iterations"],
+            "rel_residual_true": comp2["rel_residual_true"], "converged": comp2["converged"]},
         "roofline": {
             "bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,

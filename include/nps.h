@@ -86,8 +86,6 @@ typedef struct {
     int n_ortho;         /* directions to A-orthogonalise against, 0..4 (paper: 2);  *
                           * 1 for NPS_PCG and NPS_FPCG                                */
     int precision;       /* enum nps_precision                                        */
-    int refine_every;    /* accepted for compatibility and ignored: the residual is   *
-                          * formed in double every iteration                          */
     int fixed_iters;     /* 1: run exactly max_iter iterations, no convergence test    */
     int method;          /* enum nps_method (0 = NPSDO)                               */
     int symmetric;       /* 1: precondition with P^T o P, the symmetric variant of    *
@@ -101,8 +99,16 @@ typedef struct {
     int status;                  /* same code nps_solve returned                      */
     double rel_residual;         /* true ||b - A x|| / ||b|| at exit, in double       */
     double rel_residual_rec;     /* the iteration's own (recursive) residual estimate */
-    int refinements;             /* true-residual recomputations performed            */
+    int refinements;             /* true-residual recomputations performed (one per   *
+                                  * iteration and one for x0: every precision forms   *
+                                  * b - A x in double from the double iterate each    *
+                                  * iteration, so the Krylov vectors never drift from *
+                                  * the true residual and no restart is needed)       */
     int n_fluid;                 /* number of fluid cells                              */
+    double t_setup_ms;           /* nps_solve: validation + setup on the stream (HIP  *
+                                  * events), ms; 0 from the request server            */
+    double t_iter_ms;            /* nps_solve: mean time per iteration after setup,   *
+                                  * result copy-out included, ms                      */
 } nps_info;
 
 typedef struct nps_net nps_net;
@@ -180,7 +186,8 @@ int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims
  * slot and its arena space at once; nps_server_poll returns NPS_PENDING (2)
  * until its result is ready, then copies x (double, full grid) to x_h,
  * fills *info, *latency_ms (submission to completion) and releases the
- * request.  Every request is solved exactly as nps_solve would solve it
+ * request; a request that failed validation (a hard error) leaves x_h
+ * untouched.  Every request is solved exactly as nps_solve would solve it
  * alone (same kernels, same per-request reductions): results do not depend
  * on what else is in flight.  Not thread-safe: one host thread per server.
  * ------------------------------------------------------------------------ */

@@ -39,6 +39,8 @@ class SolveInfo:
     rel_residual_rec: float
     refinements: int
     n_fluid: int
+    t_setup_ms: float = 0.0
+    t_iter_ms: float = 0.0
 
     @property
     def status_name(self) -> str:
@@ -102,7 +104,7 @@ class Net:
 
 
 def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, max_iter: int = 1000,
-          n_ortho: int | None = None, precision: int = FP32, refine_every: int = 0, fixed_iters: bool = False,
+          n_ortho: int | None = None, precision: int = FP32, fixed_iters: bool = False,
           x: torch.Tensor | None = None, ws: torch.Tensor | None = None, check: bool = True, method: int = 0,
           symmetric: bool = False):
     """x, info = solve(...): labels uint8 (nz,ny,nx), b float64, both on device.
@@ -119,7 +121,7 @@ def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, ma
         raise ValueError("labels must be uint8 and b float64")
     if x is None:
         x = torch.empty_like(b)
-    opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, refine_every, 1 if fixed_iters else 0, method,
+    opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 1 if fixed_iters else 0, method,
                          1 if symmetric else 0)
     if ws is None:
         nbytes = _lib.nps_solve_workspace_bytes(_dims(labels.shape), net.levels, opts)
@@ -131,7 +133,7 @@ def solve(net: Net, labels: torch.Tensor, b: torch.Tensor, tol: float = 1e-6, ma
     if rc < 0 and check and rc != _lib.NPS_EBREAKDOWN:
         raise NpsError(rc, "nps_solve")
     return x, SolveInfo(info.iterations, rc, info.rel_residual, info.rel_residual_rec,
-                        info.refinements, info.n_fluid)
+                        info.refinements, info.n_fluid, info.t_setup_ms, info.t_iter_ms)
 
 
 def apply_laplacian(labels: torch.Tensor, x: torch.Tensor, y: torch.Tensor | None = None) -> torch.Tensor:
@@ -262,7 +264,7 @@ class Server:
         self._shapes = {}
 
     def request_bytes(self, shape, tol=1e-6, max_iter=1000, n_ortho=2, precision=MIXED_BF16, method=0) -> int:
-        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 0, method, 0)
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, method, 0)
         return _lib.nps_server_request_bytes(self.handle, _dims(shape), opts)
 
     def submit(self, labels: np.ndarray, b: np.ndarray, tol: float = 1e-6, max_iter: int = 1000,
@@ -271,7 +273,7 @@ class Server:
         bb = np.ascontiguousarray(b, dtype=np.float64)
         if lab.shape != bb.shape or lab.ndim != 3:
             raise ValueError("labels and b must be (nz, ny, nx) arrays of one shape")
-        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, 1 if fixed_iters else 0, method, 0)
+        opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 1 if fixed_iters else 0, method, 0)
         rc, rid = _lib.nps_server_submit(self.handle, lab.ctypes.data, _dims(lab.shape), bb.ctypes.data, opts)
         if rc != _lib.NPS_OK:
             raise NpsError(rc, "nps_server_submit")
@@ -292,6 +294,8 @@ class Server:
         if rc == _lib.NPS_PENDING:
             return None
         del self._shapes[rid]
+        if rc < 0 and rc != _lib.NPS_EBREAKDOWN:
+            x = None   # rejected before its solve ran: no solution
         return x, SolveInfo(info.iterations, rc, info.rel_residual, info.rel_residual_rec, info.refinements,
                             info.n_fluid), lat
 
@@ -356,15 +360,33 @@ def net_backward(net: Net, labels: torch.Tensor, r: torch.Tensor, gy: torch.Tens
     return grad
 
 
+_net_cache: list = [None]   # (weak reference to the params tensor, its version, levels, device, Net)
+
+
+def _cached_net(params: torch.Tensor, levels: int, device) -> Net:
+    """The device network of a parameter tensor, rebuilt only when another
+    tensor is passed, the tensor was modified in place (its version counter
+    moved) or the level count or device changed."""
+    import weakref
+    c = _net_cache[0]
+    if c is not None and c[0]() is params and c[1:4] == (params._version, levels, str(device)):
+        return c[4]
+    net = Net(params.detach().cpu().numpy(), levels, device=device)
+    _net_cache[0] = (weakref.ref(params), params._version, levels, str(device), net)
+    return net
+
+
 class Precond(torch.autograd.Function):
     """y = P(I, r) with the library's forward and hand-written backward.
 
-    params: float64 tensor (nps_param_count(levels)); the gradient flows to it.
-    Each call keeps its own activation workspace until backward."""
+    params: float64 tensor (nps_param_count(levels)); gradients flow to it
+    (nps_net_backward) and to r (P is linear in r: dL/dr = P^T dL/dy, the
+    library's adjoint).  Each call keeps its own activation workspace until
+    backward."""
 
     @staticmethod
     def forward(ctx, params, labels, r, levels):
-        net = Net(params.detach().cpu().numpy(), levels, device=r.device)
+        net = _cached_net(params, levels, r.device)
         ws = train_workspace(labels.shape, levels, FP64 if r.dtype == torch.float64 else FP32, device=r.device)
         y = net_forward(net, labels, r.contiguous(), ws)
         ctx.net, ctx.ws, ctx.labels, ctx.levels = net, ws, labels, levels
@@ -374,17 +396,24 @@ class Precond(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gy):
         (r,) = ctx.saved_tensors
-        grad = torch.zeros(_lib.nps_param_count(ctx.levels), dtype=torch.float64, device=r.device)
-        net_backward(ctx.net, ctx.labels, r.contiguous(), gy.contiguous().to(r.dtype), grad, ctx.ws)
+        gy = gy.contiguous().to(r.dtype)
+        grad = None
+        if ctx.needs_input_grad[0]:
+            grad = torch.zeros(_lib.nps_param_count(ctx.levels), dtype=torch.float64, device=r.device)
+            net_backward(ctx.net, ctx.labels, r.contiguous(), gy, grad, ctx.ws)
+        gr = apply_precond_transpose(ctx.net, ctx.labels, gy, ws=ctx.ws) if ctx.needs_input_grad[2] else None
         ctx.ws = None
-        return grad, None, None, None
+        return grad, None, gr, None
 
 
 class TrainLoss(torch.autograd.Function):
-    """loss = || b - A y ||_2 (A the mixed-BC matrix of the labels)."""
+    """loss = || b - A y ||_2 (A the mixed-BC matrix of the labels).
+    Differentiable in y only: b is data."""
 
     @staticmethod
     def forward(ctx, y, labels, b, levels):
+        if b.requires_grad:
+            raise NotImplementedError("TrainLoss has no gradient with respect to b")
         ws = train_workspace(labels.shape, levels, FP64 if y.dtype == torch.float64 else FP32, device=y.device)
         loss, gy = train_loss(labels, b.contiguous(), y.contiguous(), levels, ws)
         ctx.save_for_backward(gy)

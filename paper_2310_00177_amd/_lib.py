@@ -34,13 +34,14 @@ class nps_dims(ctypes.Structure):
 
 class nps_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int), ("n_ortho", ctypes.c_int),
-                ("precision", ctypes.c_int), ("refine_every", ctypes.c_int), ("fixed_iters", ctypes.c_int),
+                ("precision", ctypes.c_int), ("fixed_iters", ctypes.c_int),
                 ("method", ctypes.c_int), ("symmetric", ctypes.c_int)]
 
 
 class nps_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int), ("status", ctypes.c_int), ("rel_residual", ctypes.c_double),
-                ("rel_residual_rec", ctypes.c_double), ("refinements", ctypes.c_int), ("n_fluid", ctypes.c_int)]
+                ("rel_residual_rec", ctypes.c_double), ("refinements", ctypes.c_int), ("n_fluid", ctypes.c_int),
+                ("t_setup_ms", ctypes.c_double), ("t_iter_ms", ctypes.c_double)]
 
 
 class nps_kernel_stat(ctypes.Structure):

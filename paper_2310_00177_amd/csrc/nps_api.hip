@@ -10,6 +10,7 @@
 #include "nps.h"
 #include "nps_internal.hpp"
 #include "nps_kernels.hpp"
+#include "nps_march_kernels.hpp"
 #include "nps_train_kernels.hpp"
 #include "nps_lanczos_kernels.hpp"
 
@@ -139,6 +140,7 @@ struct Layout {
     size_t k1[kMaxLevels + 1], k2[kMaxLevels + 1];
     size_t dhat, dring[kRing], adring[kRing], x[2], r[2];
     size_t wmode[kMaxLevels + 1][2];   // per-wave CConv modes: [level][down, up (level 1)]
+    size_t gmode[2];                   // level 1 on matrix cores: per-group modes [down, up]
     size_t total;
 };
 
@@ -169,6 +171,10 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
         const size_t waves = (size_t)tiles_of(level_grid(d, l)).count() * TZ;
         L.wmode[l][0] = put(waves);
         if (l == 1) L.wmode[l][1] = put(waves);
+    }
+    if (is_mfma(p.km[1])) {
+        L.gmode[0] = put(group_mode_bytes(level_grid(d, 1)));
+        L.gmode[1] = put(group_mode_bytes(level_grid(d, 1)));
     }
     L.dhat = put(s * n);
     if (solve) {
@@ -484,10 +490,19 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
                                                            nullptr);
         }));
     }
+    if (is_mfma(plan.km[1])) {
+        const Grid g = level_grid(d, 1);
+        const size_t threads = group_mode_bytes(g) * 16;
+        NPS_TRY(launch("setup_group_modes", (double)ncells(g), s, [&] {
+            k_group_modes<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+                labels, g, mptr<uint8_t>(ws, lay.gmode[0]), mptr<uint8_t>(ws, lay.gmode[1]));
+        }));
+    }
     for (int l = 1; l <= L; ++l) {
         const Grid g = level_grid(d, l);
         const int grid = tile_grid(g);
         int8_t* md = mptr<int8_t>(ws, lay.wmode[l][0]);
+        if (l == 1 && is_mfma(plan.km[1])) continue;   // the marching kernels use the group modes
         if (l == 1)
             NPS_TRY(launch("setup_wave_modes", (double)ncells(g), s, [&] {
                 k_wave_modes<true><<<grid, kBlock, 0, s>>>(img(l), g, 1u, md, mptr<int8_t>(ws, lay.wmode[l][1]));
@@ -648,11 +663,19 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
     const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k1[1]) : nullptr;
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        const int grid = persist_grid(&k_down_l1<T, KM>, g);
-        return launch("net_down_l1", (double)ncells(g), s, [&] {
-            k_down_l1<T, KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, kst, st,
-                                                     cptr<int8_t>(ws, lay.wmode[1][0]));
-        });
+        if constexpr (is_mfma(KM)) {
+            const int grid = persist_grid_n(&k_down_l1m<KM>, columns_of(g).count());
+            return launch("net_down_l1", (double)ncells(g), s, [&] {
+                k_down_l1m<KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, st,
+                                                       cptr<uint32_t>(ws, lay.gmode[0]));
+            });
+        } else {
+            const int grid = persist_grid(&k_down_l1<T, KM>, g);
+            return launch("net_down_l1", (double)ncells(g), s, [&] {
+                k_down_l1<T, KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, kst, st,
+                                                         cptr<int8_t>(ws, lay.wmode[1][0]));
+            });
+        }
     });
 }
 
@@ -670,12 +693,21 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k2[1]) : nullptr;
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
-        const int grid = persist_grid(&k_up_l1<T, KM, HOOK>, g);
-        if (nparts) *nparts = grid;
-        return launch("net_up_l1", (double)ncells(g), s, [&] {
-            k_up_l1<T, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, kst, st, partials, ad[0], ad[1],
-                                                        ad[2], ad[3], nullptr, cptr<int8_t>(ws, lay.wmode[1][1]));
-        });
+        if constexpr (is_mfma(KM)) {
+            const int grid = persist_grid_n(&k_up_l1m<KM, HOOK>, columns_of(g).count());
+            if (nparts) *nparts = grid;
+            return launch("net_up_l1", (double)ncells(g), s, [&] {
+                k_up_l1m<KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, st, partials, ad[0], ad[1],
+                                                          ad[2], ad[3], cptr<uint32_t>(ws, lay.gmode[1]));
+            });
+        } else {
+            const int grid = persist_grid(&k_up_l1<T, KM, HOOK>, g);
+            if (nparts) *nparts = grid;
+            return launch("net_up_l1", (double)ncells(g), s, [&] {
+                k_up_l1<T, KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, kst, st, partials, ad[0], ad[1],
+                                                            ad[2], ad[3], nullptr, cptr<int8_t>(ws, lay.wmode[1][1]));
+            });
+        }
     });
 }
 
@@ -971,12 +1003,26 @@ Solver* make_solver(int precision) {
 }
 
 // nps_solve: validate, set up, iterate with a one-body-behind poll, finalize.
+// Events bracketing a solve's phases on its stream (created once per thread).
+struct SolveEvents {
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};   // start, setup done, end
+    bool ok = false;
+    SolveEvents() {
+        ok = true;
+        for (auto& e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    }
+};
+
 int run_solve(Solver& sv, double* x_out, nps_info* info) {
+    thread_local SolveEvents tev;
+    if (!tev.ok) return fail(NPS_EDEVICE, "hipEventCreate failed");
+    NPS_HIP(hipEventRecord(tev.ev[0], sv.s));
     NPS_TRY(sv.enqueue_validate());
     NPS_HIP(hipStreamSynchronize(sv.s));
     NPS_TRY(validation_status(sv.hs));
     if (sv.hs->bb != 0.0) {
         NPS_TRY(sv.enqueue_setup());
+        NPS_HIP(hipEventRecord(tev.ev[1], sv.s));
         const int max_iter = std::max(sv.o.max_iter, 0);
         volatile HostFlags* hf = sv.hf;
         for (int k = 1; k <= max_iter + 1; ++k) {
@@ -996,10 +1042,19 @@ int run_solve(Solver& sv, double* x_out, nps_info* info) {
             }
             if (hf->done) break;
         }
+    } else {
+        NPS_HIP(hipEventRecord(tev.ev[1], sv.s));
     }
     NPS_TRY(sv.enqueue_finalize(x_out));
+    NPS_HIP(hipEventRecord(tev.ev[2], sv.s));
     NPS_HIP(hipStreamSynchronize(sv.s));
-    return fill_info(sv.hs, info);
+    const int rc = fill_info(sv.hs, info);
+    float setup_ms = 0.0f, iter_ms = 0.0f;
+    NPS_HIP(hipEventElapsedTime(&setup_ms, tev.ev[0], tev.ev[1]));
+    NPS_HIP(hipEventElapsedTime(&iter_ms, tev.ev[1], tev.ev[2]));
+    info->t_setup_ms = setup_ms;
+    info->t_iter_ms = info->iterations > 0 ? iter_ms / info->iterations : 0.0;
+    return rc;
 }
 
 template <class T>
@@ -1086,6 +1141,7 @@ struct Request {
     uint8_t* lab_h = nullptr;   // pinned copies of the inputs
     double* b_h = nullptr;
     double* x_h = nullptr;      // pinned result
+    bool x_ready = false;       // x_h was written (the request reached its finalize step)
     Phase phase = kQueued;
     int status = NPS_OK;
     nps_info info{};
@@ -1193,6 +1249,7 @@ int enqueue_finish(nps_server* srv, Slot& sl) {
     NPS_TRY(sl.sv->enqueue_finalize(x_d));
     NPS_HIP(hipMemcpyAsync(r->x_h, x_d, 8 * r->n, hipMemcpyDeviceToHost, sl.s));
     NPS_HIP(hipEventRecord(sl.ev[0], sl.s));
+    r->x_ready = true;
     r->phase = Request::kFinishing;
     return NPS_OK;
 }
@@ -2058,7 +2115,8 @@ int nps_server_poll(nps_server* srv, uint64_t req_id, double* x_h, nps_info* inf
     if (it == srv->live.end()) return fail(NPS_EINVAL, "unknown request %llu", (unsigned long long)req_id);
     Request* r = it->second;
     if (r->phase != Request::kDone) return NPS_PENDING;
-    if (x_h) std::memcpy(x_h, r->x_h, 8 * r->n);
+    // a request rejected before its solve ran leaves x_h untouched (hard error)
+    if (x_h && r->x_ready) std::memcpy(x_h, r->x_h, 8 * r->n);
     if (info) *info = r->info;
     if (info) info->status = r->status;
     if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(r->t_done - r->t_submit).count();

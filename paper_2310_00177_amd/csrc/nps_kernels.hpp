@@ -1,24 +1,27 @@
 // HIP kernels for gfx950 (CDNA4) of the neural-preconditioned Poisson solve.
 //
-// One NPSDO iteration (Alg. 1) is a fixed sequence of launches:
-//   down_l1     x_k = x_(k-1) + alpha_k d_k, the literal residual r_k = b - A x_k,
-//               CConv_1^1(r_k) and its 2x average pool; partial ||r_k||^2
-//   control     ||r_k||, convergence, iteration count
-//   down/up     Alg. 2 on the coarser levels (CConv_1 + pool down; trilinear
-//               upsampling + CConv_2 + c1 x1 + c2 x2 up), the smallest levels
-//               in one workgroup ("bottom")
+// One NPSDO iteration (Alg. 1) is a fixed sequence of launches, none of them
+// a control kernel; each scalar stage of Alg. 1 runs inside the first kernel
+// that needs its result:
+//   residual    Step stage (alpha = r.d / d.Ad of the previous direction, or
+//               a breakdown), x += alpha d, the literal residual r = b - A x
+//               (double), partial ||r||^2
+//   down_l1     CConv_1^1(r) and its 2x average pool (Alg. 2, first level)
+//   down        CConv_1^l + pool on the coarser levels
+//   bottom      the smallest levels in one workgroup (down, coarsest CConv,
+//               up) and the Residual stage: ||r||, the convergence test, 1/||r||
+//   up          trilinear upsampling + CConv_2^l + c1 x1 + c2 x2
 //   up_l1       dhat = P(r)/||r|| on fluid cells; partial dhat . A d_i
-//   control     beta_i = dhat . A d_i / d_i . A d_i
-//   ortho       d = dhat - sum beta_i d_i, A d; partial d . A d, r . d
-//   control     alpha = r . d / d . A d, breakdown test
+//   ortho       Dots stage (beta_i = dhat . A d_i / d_i . A d_i), d = dhat -
+//               sum beta_i d_i, A d; partial d . A d, r . d
 // The per-cell kernels K_t(p) of a level are either regenerated from the
 // labels on chip every application (MFMA for the large levels, vector ALU in
 // FP64) or, for levels of at most 32768 cells, formed once per solve.
 //
 // No kernel synchronises across workgroups: each reduction writes one
-// partial per block, and the one-block control kernel that follows sums them
-// in block order (deterministic) and updates the solver state.  Kernel
-// boundaries provide the cross-XCD visibility.
+// partial per block, and the kernel that consumes the sum adds the partials
+// in block order (deterministic).  Kernel boundaries provide the cross-XCD
+// visibility.
 #pragma once
 
 #include "nps_internal.hpp"

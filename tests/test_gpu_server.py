@@ -93,6 +93,7 @@ def test_bad_request_fails_alone(net):
     res, _ = drain(srv, ids)
     assert res[ids[0]][1].status == 0
     assert res[ids[1]][1].status == -3
+    assert res[ids[1]][0] is None   # a rejected request returns no solution
     with pytest.raises(nps.NpsError):
         srv.submit(good[0][:, :, :16].copy(), good[1][:, :, :16].copy())   # 16 % 32
     srv.close()

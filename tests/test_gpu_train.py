@@ -104,3 +104,27 @@ def test_autograd_functions_match_oracle_batch_mean():
     loss_ref, grad_ref = og.batch_loss_and_grad(params, L, labs, bs)
     assert loss.item() == pytest.approx(loss_ref, rel=1e-11)
     assert rel(p.grad.cpu().numpy(), grad_ref) <= 1e-9
+
+
+def test_autograd_input_gradient_is_the_adjoint():
+    """P is linear in r, so dL/dr = P^T dL/dy: Precond's gradient for r equals
+    the oracle's transpose apply of the loss gradient (FP64)."""
+    spec, L = CASES["grad16"]
+    lab = gi.gen_labels(spec, seed=31)
+    b = gi.gen_rhs(lab, seed=32, normalize=True)
+    params = params_with_biases(L, 17)
+    p = torch.tensor(params, dtype=torch.float64, device="cuda", requires_grad=True)
+    labels = torch.from_numpy(lab).cuda()
+    r = torch.from_numpy(np.random.default_rng(33).standard_normal(lab.shape)).cuda().requires_grad_(True)
+    gy = np.random.default_rng(34).standard_normal(lab.shape)
+    y = nps.Precond.apply(p, labels, r, L)
+    (y * torch.from_numpy(gy).cuda()).sum().backward()
+    ref = og.transpose_apply(onet.Network(params, L, lab), gy)
+    assert rel(r.grad.cpu().numpy(), ref) <= 1e-12
+    assert p.grad is not None
+    # a second call with the same parameter tensor reuses its device network
+    net = nps._cached_net(p, L, r.device)
+    assert nps._cached_net(p, L, r.device) is net
+    with torch.no_grad():
+        p.mul_(1.0)          # an in-place update moves the version: rebuilt
+    assert nps._cached_net(p, L, r.device) is not net
