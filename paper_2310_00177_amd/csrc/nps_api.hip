@@ -683,7 +683,7 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
 // grid (the number of partials).
 template <class T, bool HOOK>
 int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
-              const T* x2, T* dhat, const T* const* ad, hipStream_t s, int* nparts) {
+              const T* x2, T* dhat, const T* const* ad, hipStream_t s, int* nparts, int max_dots = 0) {
     const Grid g = level_grid(d, 1);
     State* st = mptr<State>(ws, lay.state);
     double* partials = mptr<double>(ws, lay.dots);
@@ -694,12 +694,23 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
         if constexpr (is_mfma(KM)) {
-            const int grid = persist_grid_n(&k_up_l1m<KM, HOOK>, columns_of(g).count());
-            if (nparts) *nparts = grid;
-            return launch("net_up_l1", (double)ncells(g), s, [&] {
-                k_up_l1m<KM, HOOK><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, st, partials, ad[0], ad[1],
-                                                          ad[2], ad[3], cptr<uint32_t>(ws, lay.gmode[1]));
-            });
+            // the kernel keeps registers for at most max_dots dot operands
+            auto go = [&](auto nd) {
+                constexpr int ND = decltype(nd)::value;
+                constexpr bool H = HOOK;
+                const int grid = persist_grid_n(&k_up_l1m<KM, H, H ? 0 : ND>, columns_of(g).count());
+                if (nparts) *nparts = grid;
+                return launch("net_up_l1", (double)ncells(g), s, [&] {
+                    k_up_l1m<KM, H, H ? 0 : ND><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, st, partials,
+                                                                       ad[0], ad[1], ad[2], ad[3],
+                                                                       cptr<uint32_t>(ws, lay.gmode[1]));
+                });
+            };
+            if (HOOK || max_dots <= 0) return go(std::integral_constant<int, 0>());
+            if (max_dots == 1) return go(std::integral_constant<int, 1>());
+            if (max_dots == 2) return go(std::integral_constant<int, 2>());
+            if (max_dots == 3) return go(std::integral_constant<int, 3>());
+            return go(std::integral_constant<int, 4>());
         } else {
             const int grid = persist_grid(&k_up_l1<T, KM, HOOK>, g);
             if (nparts) *nparts = grid;
@@ -949,7 +960,8 @@ struct SolverT : Solver {
         NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s));
         if (res_in_bottom) NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2, pdots, np_res, hf_d));
         else NPS_TRY(run_coarse<T>(net, d, plan, lay, ws, s, &x2));
-        NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np)));
+        NPS_TRY((run_up_l1<T, false>(net, labels, d, plan, lay, ws, x2, dhat, ad, s, &np,
+                                     o.symmetric ? 0 : (o.method == NPS_NPSDO ? o.n_ortho : o.method == NPS_PCG ? 1 : 2))));
         if (o.symmetric) {   // d^ = P^T P(r)/||r||, then the dots the up kernel left out
             T* dsym = mptr<T>(ws, tl.dsym);
             NPS_TRY(adjoint_apply<T>(net, labels, d, tl, ws, dhat, dsym, s));

@@ -213,11 +213,11 @@ struct RLab {   // CConv input and label of one staged cell
 
 // x1 = CConv_1^1(r) and r^2 = Pool(x1) (the input masked to fluid).  Plane-
 // marching: step s writes plane s into the ring, issues the loads of plane
-// s + 1, then forms output plane s - 1.  The 2x2x2 pool sums x pairs with a
+// s + 2, then forms output plane s - 1.  The 2x2x2 pool sums x pairs with a
 // DPP quad permutation, y pairs with a permlane swap and z pairs in a
 // register (chunks start on even planes and have even length).
 template <int KM>
-__global__ __launch_bounds__(kBlock) void k_down_l1m(const uint8_t* __restrict__ lab, Grid g,
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4) void k_down_l1m(const uint8_t* __restrict__ lab, Grid g,
                                                      const float* __restrict__ r, float* __restrict__ x1,
                                                      float* __restrict__ rnext, const CConvW<float>* __restrict__ w,
                                                      const MfmaW* __restrict__ wm, const State* st,
@@ -246,7 +246,9 @@ __global__ __launch_bounds__(kBlock) void k_down_l1m(const uint8_t* __restrict__
         const bool col = xx < g.nx && yy < g.ny;
         const uint32_t* mrow = gmode + ((size_t)cy * cl.ncx + cx) * 4 + wv;   // + z * ncy * ncx * 4 words
         const size_t mstride = (size_t)cl.ncy * cl.ncx * 4;
-        auto pre = plane(x0, y0, z0 - 1);
+        // planes are loaded two steps ahead of their staging
+        auto preA = plane(x0, y0, z0 - 1);
+        auto preB = plane(x0, y0, z0);
         if (first) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
             if (done) return;
@@ -254,14 +256,14 @@ __global__ __launch_bounds__(kBlock) void k_down_l1m(const uint8_t* __restrict__
         }
         __syncthreads();   // the previous footprint's reads of the ring are done
         float pool = 0.0f;
-        for (int s = z0 - 1; s <= z1; ++s) {
+        auto step = [&](int s, auto& pre) {
             uint2* buf = ring + (s & 3) * kPlaneP;
             put_batch(pre, [&](int i, RLab e) { buf[i] = march_record<KM>(e.r, e.l); });
-            if (s < z1) pre = plane(x0, y0, s + 1);
+            if (s + 2 <= z1) pre = plane(x0, y0, s + 2);
             const int c = s - 1;
             const uint32_t modes = c >= z0 ? __builtin_amdgcn_readfirstlane(mrow[(size_t)c * mstride]) : 0u;
             __syncthreads();   // plane s is staged
-            if (c < z0) continue;
+            if (c < z0) return;
             const float out = march_cconv<KM>(ring, c, modes, mc);
             if (col) x1[cell_index(g, c, yy, xx)] = out;
             // 2x2x2 pool: x pair (DPP quad_perm [1,0,3,2]), y pair (rows 2k, 2k+1)
@@ -273,6 +275,11 @@ __global__ __launch_bounds__(kBlock) void k_down_l1m(const uint8_t* __restrict__
                     rnext[cell_index(gc, c >> 1, yy >> 1, xx >> 1)] = pool * 0.125f;
                 pool = 0.0f;
             }
+        };
+        // z1 - z0 is even, so the steps z0 - 1 .. z1 come in pairs
+        for (int s = z0 - 1; s <= z1; s += 2) {
+            step(s, preA);
+            step(s + 1, preB);
         }
     }
 }
@@ -287,25 +294,30 @@ __global__ __launch_bounds__(kBlock) void k_down_l1m(const uint8_t* __restrict__
 constexpr int kCX = PX / 2 + 2, kCY = PY / 2 + 2, kCPlane = kCX * kCY;
 static_assert(kCPlane <= kBlock, "one coarse cell per thread");
 
+template <int ND>
 struct UpCell {   // operands of the lane's own cell for one output plane
     float x1;
-    float ad[kMaxOrtho];
+    float ad[ND > 0 ? ND : 1];
 };
 
-template <int KM, bool HOOK>
-__global__ __launch_bounds__(kBlock) void k_up_l1m(const uint8_t* __restrict__ lab, Grid g,
+// ND: the most dots the state can ask for (NPSDO: n_ortho; PCG 1; flexible
+// PCG 2; 0 for the hook and the symmetric variant); HOOK: the parity hook
+// (no scaling, no dots).
+template <int KM, bool HOOK, int ND>
+__global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4) void k_up_l1m(const uint8_t* __restrict__ lab, Grid g,
                                                    const float* __restrict__ xc, const float* __restrict__ x1,
                                                    float* __restrict__ dhat, const CConvW<float>* __restrict__ w,
                                                    const MfmaW* __restrict__ wm, const State* st,
                                                    double* __restrict__ partials, const float* __restrict__ ad0,
                                                    const float* __restrict__ ad1, const float* __restrict__ ad2,
                                                    const float* __restrict__ ad3, const uint32_t* __restrict__ gmode) {
+    static_assert(!HOOK || ND == 0, "the hook forms no dots");
     __shared__ uint2 ring[4 * kPlaneP];
     __shared__ float csh[3][kCPlane];
     const int done = st->done;
     const float c1 = (float)st->c1[0], c2 = (float)st->c2[0];
     const float scale = HOOK ? 1.0f : (float)st->scale;
-    const int ndots = HOOK || st->sym ? 0 : st->ndots;   // the symmetric variant dots after P^T
+    const int ndots = HOOK || st->sym ? 0 : min(st->ndots, ND);   // the symmetric variant dots after P^T
     const MarchCtx<KM> mc = march_ctx<KM>(wm, w);
     const Columns cl = columns_of(g);
     const Grid gc = coarser(g);
@@ -332,13 +344,13 @@ __global__ __launch_bounds__(kBlock) void k_up_l1m(const uint8_t* __restrict__ l
     auto put_coarse = [&](int m, float val) {
         if (threadIdx.x < kCPlane) csh[(m + 3) % 3][threadIdx.x] = val;
     };
-    // the lane cell's operands of output plane zz
+    // the lane cell's operands of output plane zz (an unused dot slot reads x1)
     auto cell_ops = [&](int zz, int yy, int xx, bool col) {
-        const size_t q = col && zz < g.nz ? cell_index(g, zz, yy, xx) : 0;
-        UpCell u;
+        const size_t q = col ? cell_index(g, zz, yy, xx) : 0;
+        UpCell<ND> u;
         u.x1 = x1[q];
 #pragma unroll
-        for (int j = 0; j < kMaxOrtho; ++j) u.ad[j] = (!HOOK && j < ndots ? adp[j] : x1)[q];
+        for (int j = 0; j < ND; ++j) u.ad[j] = (j < ndots ? adp[j] : x1)[q];
         return u;
     };
     bool first = true;
@@ -352,10 +364,13 @@ __global__ __launch_bounds__(kBlock) void k_up_l1m(const uint8_t* __restrict__ l
         const uint32_t* mrow = gmode + ((size_t)cy * cl.ncx + cx) * 4 + wv;
         const size_t mstride = (size_t)cl.ncy * cl.ncx * 4;
         const int m0 = z0 / 2;
+        // loads run two steps ahead: fine-plane labels, the coarse plane the
+        // next even step writes, the cell operands of the plane a step computes
         const float cm0 = coarse(x0, y0, m0 - 1), cm1 = coarse(x0, y0, m0);
-        auto lpre = labels(x0, y0, z0 - 1);
-        float cpre = 0.0f;
-        UpCell opre = cell_ops(z0, yy, xx, col), ocur;
+        float cpre = coarse(x0, y0, m0 + 1);
+        auto lA = labels(x0, y0, z0 - 1);
+        auto lB = labels(x0, y0, z0);
+        UpCell<ND> oA, oB;
         if (first) {
             __asm__ volatile("" ::: "memory");
             if (done) return;
@@ -365,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_up_l1m(const uint8_t* __restrict__ l
         put_coarse(m0 - 1, cm0);
         put_coarse(m0, cm1);
         __syncthreads();
-        for (int s = z0 - 1; s <= z1; ++s) {
+        auto step = [&](int s, auto& lpre, UpCell<ND>& ops) {
             // stage fine plane s: interpolation from coarse planes s >> 1 and its neighbour on s's side
             uint2* buf = ring + (s & 3) * kPlaneP;
             const bool zin = s >= 0 && s < g.nz;
@@ -392,29 +407,32 @@ __global__ __launch_bounds__(kBlock) void k_up_l1m(const uint8_t* __restrict__ l
                 // the CConv_2 input is not masked (only the level's output is)
                 buf[i] = uint2{bits(val), feat_word<KM, true>(l)};
             });
-            // coarse plane (s >> 1) + 1 for the odd fine plane s + 1
-            if (!(s & 1) && s < z1) put_coarse((s >> 1) + 1, cpre);
-            if (s < z1) lpre = labels(x0, y0, s + 1);
-            if ((s & 1) && s + 1 < z1) cpre = coarse(x0, y0, ((s + 1) >> 1) + 1);
-            const int c = s - 1;
-            if (c >= z0) {   // operands of plane c were loaded a step ago; issue those of plane s
-                ocur = opre;
-                if (s < z1) opre = cell_ops(s, yy, xx, col);
+            // an even step writes coarse plane (s >> 1) + 1, which the odd fine plane s + 1 needs
+            if (!(s & 1) && s < z1) {
+                put_coarse((s >> 1) + 1, cpre);
+                if (s + 2 < z1) cpre = coarse(x0, y0, (s >> 1) + 2);
             }
+            if (s + 2 <= z1) lpre = labels(x0, y0, s + 2);
+            const int c = s - 1;
             const uint32_t modes = c >= z0 ? __builtin_amdgcn_readfirstlane(mrow[(size_t)c * mstride]) : 0u;
             __syncthreads();   // plane s (and the coarse plane) staged
-            if (c < z0) continue;
-            const float x2 = march_cconv<KM>(ring, c, modes, mc);
-            const bool fl = ring[(c & 3) * kPlaneP + own].y == fluid_word;
-            const float out = fl ? (c1 * ocur.x1 + c2 * x2) * scale : 0.0f;
-            if (col) {
-                dhat[cell_index(g, c, yy, xx)] = out;
-                if (!HOOK) {
+            if (c >= z0) {
+                const float x2 = march_cconv<KM>(ring, c, modes, mc);
+                const bool fl = ring[(c & 3) * kPlaneP + own].y == fluid_word;
+                const float out = fl ? (c1 * ops.x1 + c2 * x2) * scale : 0.0f;
+                if (col) {
+                    dhat[cell_index(g, c, yy, xx)] = out;
 #pragma unroll
-                    for (int j = 0; j < kMaxOrtho; ++j)
-                        if (j < ndots) v[j] = fma((double)out, (double)ocur.ad[j], v[j]);
+                    for (int j = 0; j < ND; ++j)
+                        if (j < ndots) v[j] = fma((double)out, (double)ops.ad[j], v[j]);
                 }
             }
+            if (s + 1 < z1) ops = cell_ops(s + 1, yy, xx, col);   // plane s + 1, formed at step s + 2
+        };
+        // z1 - z0 is even, so the steps z0 - 1 .. z1 come in pairs
+        for (int s = z0 - 1; s <= z1; s += 2) {
+            step(s, lA, oA);
+            step(s + 1, lB, oB);
         }
     }
     if (!HOOK && !done) block_partials<kBlock>(v, partials);
