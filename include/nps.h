@@ -172,6 +172,21 @@ int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims
                       const void* r_d, void* d_d, int precision,
                       void* ws_d, size_t ws_bytes, void* stream);
 
+/* nps_apply_precond without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same kernels and results as
+ * nps_apply_precond; its scratch is a static device array of 128 MiB
+ * (134,217,728 bytes) that each GPU the library runs on holds until the
+ * process ends, so the call allocates nothing.  Grids whose network
+ * evaluation needs more scratch than that (about 10 bytes per cell in FP32
+ * and the mixed modes, 20 in FP64, plus the stored kernels of the coarse
+ * levels: 224^3 fits in FP32, 160^3 in FP64, 256^3 does not) are rejected
+ * with NPS_ENOMEM before any work is enqueued.  Every call on one GPU shares
+ * that GPU's array: calls that overlap on one GPU (other streams, other host
+ * threads) race; serialise them.  Not synchronised. */
+int nps_apply_precond_noalloc(const nps_net* net, const uint8_t* labels_d, nps_dims dims,
+                              const void* r_d, void* d_d, int precision, void* stream);
+
 /* ------------------------------------------------------------------------
  * Request server: continuous batching of solves of different grids.
  *

@@ -20,7 +20,7 @@ from ._lib import (NPS_FP64 as FP64, NPS_FP32 as FP32, NPS_MIXED_BF16 as MIXED_B
                    NPS_MIXED_FP16 as MIXED_FP16, NPS_NPSDO as NPSDO, NPS_PCG as PCG, NPS_FPCG as FPCG,
                    STATUS_NAMES)
 
-__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "apply_precond_transpose", "asymmetry", "lanczos", "ritz_rhs", "NpsError", "SolveInfo", "Server",
+__all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "apply_precond_noalloc", "apply_precond_transpose", "asymmetry", "lanczos", "ritz_rhs", "NpsError", "SolveInfo", "Server",
            "train_workspace", "net_forward", "net_backward", "train_loss", "Precond", "TrainLoss",
            "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "NPSDO", "PCG", "FPCG", "workspace", "vector_dtype"]
 
@@ -166,6 +166,23 @@ def apply_precond(net: Net, labels: torch.Tensor, r: torch.Tensor, precision: in
                                 precision, _aligned(ws), ws_bytes, _stream())
     if rc != _lib.NPS_OK:
         raise NpsError(rc, "nps_apply_precond")
+    return d
+
+
+def apply_precond_noalloc(net: Net, labels: torch.Tensor, r: torch.Tensor, precision: int | None = None,
+                          d: torch.Tensor | None = None) -> torch.Tensor:
+    """d = P(I, r) with the library's static scratch (nps_apply_precond_noalloc:
+    the library allocates nothing; pass d to allocate nothing here either)."""
+    _check_device(labels, r)
+    if precision is None:
+        precision = FP64 if r.dtype == torch.float64 else FP32
+    if r.dtype != vector_dtype(precision):
+        raise ValueError(f"r must be {vector_dtype(precision)} for precision {precision}")
+    d = torch.empty_like(r) if d is None else d
+    rc = _lib.nps_apply_precond_noalloc(net.handle, labels.data_ptr(), _dims(labels.shape), r.data_ptr(),
+                                        d.data_ptr(), precision, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_apply_precond_noalloc")
     return d
 
 

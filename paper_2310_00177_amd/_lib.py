@@ -82,6 +82,8 @@ _lib.nps_apply_laplacian.argtypes = [_vp, nps_dims, _vp, _vp, _int, _vp]
 _lib.nps_apply_laplacian.restype = _int
 _lib.nps_apply_precond.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _int, _vp, _sz, _vp]
 _lib.nps_apply_precond.restype = _int
+_lib.nps_apply_precond_noalloc.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _int, _vp]
+_lib.nps_apply_precond_noalloc.restype = _int
 _u64 = ctypes.c_uint64
 _lib.nps_server_create.argtypes = [_vp, _sz, _int, ctypes.POINTER(_vp)]
 _lib.nps_server_create.restype = _int
@@ -109,7 +111,8 @@ _lib.nps_last_error.argtypes, _lib.nps_last_error.restype = [], ctypes.c_char_p
 
 EXPORTED = ["nps_param_count", "nps_net_bytes", "nps_net_create", "nps_net_destroy", "nps_net_levels",
             "nps_workspace_bytes", "nps_solve_workspace_bytes", "nps_solve", "nps_apply_laplacian",
-            "nps_apply_precond", "nps_apply_precond_transpose", "nps_asymmetry", "nps_lanczos_workspace_bytes",
+            "nps_apply_precond", "nps_apply_precond_noalloc",
+            "nps_apply_precond_transpose", "nps_asymmetry", "nps_lanczos_workspace_bytes",
             "nps_lanczos", "nps_ritz_workspace_bytes", "nps_ritz_rhs", "nps_server_create",
             "nps_server_destroy", "nps_server_request_bytes", "nps_server_submit", "nps_server_step",
             "nps_server_poll", "nps_train_workspace_bytes", "nps_net_forward", "nps_train_loss", "nps_net_backward",
@@ -193,6 +196,11 @@ def nps_solve(net: int, labels_d: int, dims: nps_dims, b_d: int, x_d: int, opts:
 
 def nps_apply_laplacian(labels_d: int, dims: nps_dims, x_d: int, y_d: int, precision: int, stream: int) -> int:
     return _lib.nps_apply_laplacian(labels_d, dims, x_d, y_d, precision, stream)
+
+
+def nps_apply_precond_noalloc(net: int, labels_d: int, dims: nps_dims, r_d: int, d_d: int, precision: int,
+                              stream: int) -> int:
+    return _lib.nps_apply_precond_noalloc(net, labels_d, dims, r_d, d_d, precision, stream)
 
 
 def nps_apply_precond(net: int, labels_d: int, dims: nps_dims, r_d: int, d_d: int, precision: int,

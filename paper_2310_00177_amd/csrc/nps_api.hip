@@ -22,6 +22,7 @@
 #include <cmath>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <cstdarg>
 #include <cstdio>
@@ -1504,6 +1505,42 @@ int train_loss(const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* w
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch of the no-allocation entry point
+// ---------------------------------------------------------------------------
+// The workspace of nps_apply_precond_noalloc: a file-scope device array that
+// every GPU the library runs on holds until the process ends.  In host code
+// `scratch` is only a stand-in symbol: its device address, different on each
+// device, comes from hipGetSymbolAddress, taken once per device with that
+// device current and kept in g_scratch_dev.
+constexpr size_t kScratchBytes = size_t(128) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// Device address of the current device's scratch.
+int scratch_address(void** out) {
+    int dev = 0;
+    NPS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(NPS_EDEVICE, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(NPS_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return NPS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 size_t nps_param_count(int levels) {
@@ -1670,6 +1707,19 @@ int nps_apply_precond(const nps_net* net, const uint8_t* labels_d, nps_dims dims
                                plan, lay, s);
 }
 
+
+int nps_apply_precond_noalloc(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, void* d_d,
+                              int precision, void* stream) {
+    if (!net || !labels_d || !r_d || !d_d) return fail(NPS_EINVAL, "null argument");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (precision < NPS_FP64 || precision > NPS_MIXED_FP16) return fail(NPS_EINVAL, "unknown precision %d", precision);
+    const size_t need = make_layout(dims, net->levels, precision, 0, false).total;
+    if (need > kScratchBytes)
+        return fail(NPS_ENOMEM, "needs %zu bytes of scratch, the static buffer holds %zu", need, kScratchBytes);
+    void* ws = nullptr;
+    NPS_TRY(scratch_address(&ws));
+    return nps_apply_precond(net, labels_d, dims, r_d, d_d, precision, ws, kScratchBytes, stream);
+}
 
 size_t nps_train_workspace_bytes(nps_dims dims, int levels, int precision) {
     if (check_dims(dims, levels) != NPS_OK) return 0;
