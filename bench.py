@@ -70,6 +70,7 @@ def parse():
     ap.add_argument("--no-variants", action="store_true", help="skip the solver-variant comparison")
     ap.add_argument("--cpu-iters", type=int, default=4, help="oracle iterations in the CPU sample")
     ap.add_argument("--train", action="store_true", help="training throughput (forward, loss, gradient) instead")
+    ap.add_argument("--batch", type=int, default=16, help="systems per training step of --train")
     ap.add_argument("--rhs-gen", action="store_true", help="Ritz-vector right-hand-side generator instead")
     ap.add_argument("--ritz", type=int, default=1600, help="Lanczos steps of --rhs-gen")
     ap.add_argument("--rhs-count", type=int, default=800, help="right-hand sides of --rhs-gen")
@@ -210,59 +211,65 @@ def serving_sweep(args):
 
 
 def train_bench(args):
-    """Training throughput (Sec. "Training"): per system, y = P(b), the loss
-    ||b - A y|| and its gradient with respect to every network parameter, on
-    the 128^3 scene in FP32 (the paper trains in FP32), plus the oracle's
-    loss-and-gradient on the 32^3 scene on one host thread for context."""
+    """Training step (Sec. "Training"; the batch of 16 systems at 128^3): the
+    mean over the batch of ||b - A P(b)|| and its gradient with respect to
+    every network parameter, through nps_train_step, in FP32 and in the bf16
+    leg (kernels from bf16-rounded weights, weight-gradient contraction on
+    bf16 matrix cores); the oracle's loss-and-gradient of one 32^3 system on
+    one host thread for context."""
     import torch
 
     import nps_inputs as gi
     import paper_2310_00177_amd as nps
 
     torch.cuda.set_device(0)
-    n = args.size
-    lab = gi.gen_labels(gi.scene_c1() if n == 32 else gi.scene_serving(n), seed=args.seed)
+    n, batch = args.size, args.batch
+    spec = gi.scene_c1() if n == 32 else gi.scene_serving(n)
+    labs = [gi.gen_labels(spec, seed=args.seed + i) for i in range(batch)]
+    bs = [gi.gen_rhs(lab, seed=100 + i, normalize=True) for i, lab in enumerate(labs)]
     params = gi.multilevel_params(6)
-    labels = torch.from_numpy(lab).cuda()
-    rhs = [torch.from_numpy(gi.gen_rhs(lab, seed=100 + i, normalize=True)).float().cuda() for i in range(4)]
+    labels = torch.from_numpy(np.stack(labs)).cuda()
+    b32 = torch.from_numpy(np.stack(bs)).float().cuda()
     net = nps.Net(params, 6)
-    ws = nps.train_workspace(lab.shape, 6, nps.FP32)
-    grad = torch.zeros(gi.param_count(6), dtype=torch.float64, device="cuda")
-
-    def step(b):
-        y = nps.net_forward(net, labels, b, ws)
-        loss, gy = nps.train_loss(labels, b, y, 6, ws)
-        nps.net_backward(net, labels, b, gy, grad, ws)
-        return loss
-
-    for i in range(args.warmup):
-        step(rhs[i % 4])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        loss = step(rhs[i % 4])
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    legs = {}
+    for name, prec in (("fp32", nps.FP32), ("bf16", nps.MIXED_BF16)):
+        ws = nps.train_workspace(labs[0].shape, 6, prec)
+        grad = torch.zeros(gi.param_count(6), dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            nps.train_step(net, labels, b32, grad, ws, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            loss = nps.train_step(net, labels, b32, grad, ws, precision=prec)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        legs[name] = {"steps_per_s": 1.0 / dt, "systems_per_s": batch / dt, "ms_per_step": dt * 1e3, "loss": loss}
+        print(f"# train {name}: {dt * 1e3:.2f} ms per {batch}-system step, {batch / dt:.1f} systems/s, loss {loss:.4f}",
+              file=sys.stderr, flush=True)
+        del ws
     cpu = None
     if not args.no_cpu_baseline:
         from threadpoolctl import threadpool_limits
 
         from oracle import gradient as og
         lab32 = gi.gen_labels(gi.scene_c1(), seed=1)
-        b32 = gi.gen_rhs(lab32, seed=2, normalize=True)
+        b32c = gi.gen_rhs(lab32, seed=2, normalize=True)
         with threadpool_limits(limits=1):
             c0 = time.perf_counter()
-            og.loss_and_grad(params, 6, lab32, b32)
+            og.loss_and_grad(params, 6, lab32, b32c)
             ct = time.perf_counter() - c0
         cpu = {"value": 1.0 / ct, "unit": "systems/s", "cores": 1, "kind": "oracle",
                "sample": f"oracle loss + adjoint gradient of one 32^3 system on 1 thread ({ct:.2f} s); "
                          f"the GPU line is at {n}^3 ({(n / 32) ** 3:.0f}x the cells)"}
-    out = {"metric": f"training systems/s (forward, loss, full parameter gradient) at {n}^3, FP32",
-           "value": 1.0 / dt, "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+    head = legs["fp32"]
+    out = {"metric": f"training steps/s (batch of {batch} systems at {n}^3: forward, loss, full parameter gradient)",
+           "value": head["steps_per_s"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"{n}^3 scene, unit-norm N(0,1) right-hand sides, L=6, {gi.param_count(6)} "
-                                  "parameters, stored kernels at every level", "loss": float(loss)},
+           "config": {"workload": f"{batch} systems of the {n}^3 scene recipe (seeds {args.seed}..{args.seed + batch - 1}), "
+                                  f"unit-norm N(0,1) right-hand sides, L=6, {gi.param_count(6)} parameters, "
+                                  "stored kernels at every level", "systems_per_s": head["systems_per_s"],
+                      "bf16_leg": legs["bf16"]},
            "cpu_baseline": cpu}
     print(json.dumps(out))
 

@@ -220,8 +220,13 @@ int nps_server_poll(nps_server* srv, uint64_t req_id, double* x_h, nps_info* inf
 
 /* ------------------------------------------------------------------------
  * Training (loss of Sec. "Training": || b - A P(I, b) ||_2 per system).
- * precision NPS_FP64 (double vectors) or NPS_FP32 (float vectors); every
- * level keeps its per-cell kernels in the workspace.
+ * precision NPS_FP64 (double vectors; parameter sums on the vector ALU),
+ * NPS_FP32 (float vectors; the weight-gradient contraction over cells on
+ * fp32 matrix cores) or NPS_MIXED_BF16 (float vectors; per-cell kernels
+ * formed from the count-form weights rounded to bf16, as on the mixed solve's
+ * matrix cores, and the weight-gradient contraction on bf16 matrix cores with
+ * fp32 accumulation); every level keeps its per-cell kernels in the
+ * workspace.
  *   nps_net_forward   y = P(I, r); keeps the per-level activations (the
  *                     down inputs, x1, the up outputs, the CConv_2 outputs)
  *                     in ws for the backward pass of the same system.
@@ -290,6 +295,21 @@ int nps_train_loss(const uint8_t* labels_d, nps_dims dims, int levels, const voi
                    void* gy_d, double* loss_h, int precision, void* ws_d, size_t ws_bytes, void* stream);
 int nps_net_backward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d,
                      const void* gy_d, double* grad_d, int precision, void* ws_d, size_t ws_bytes, void* stream);
+
+/* One training step over a batch (Sec. "Training": the loss averaged over a
+ * batch of systems): for each system i < batch, y_i = P(I_i, b_i) and
+ * loss_i = || b_i - A_i y_i ||_2; adds d(mean_i loss_i)/dparams into grad_d
+ * (double, nps_param_count(levels), blob layout of nps_net_create; not
+ * zeroed) and writes the mean loss to *loss_h.
+ *   labels_d  uint8[batch][nz*ny*nx]  the systems' labels, back to back.
+ *   b_d       [batch][nz*ny*nx]       right-hand sides (double for NPS_FP64,
+ *                                     float otherwise), zero off fluid.
+ * The systems run one after another in one workspace of
+ * nps_train_workspace_bytes(dims, levels, precision) bytes: each forward
+ * keeps its per-level activations for its own backward pass.  Synchronises
+ * the stream (the loss is a host value). */
+int nps_train_step(const nps_net* net, const uint8_t* labels_d, nps_dims dims, int batch, const void* b_d,
+                   double* grad_d, double* loss_h, int precision, void* ws_d, size_t ws_bytes, void* stream);
 
 /* Per-kernel timing.  While enabled (on != 0, per calling thread), every
  * kernel the library launches is bracketed by a pair of HIP events recorded

@@ -21,7 +21,7 @@ from ._lib import (NPS_FP64 as FP64, NPS_FP32 as FP32, NPS_MIXED_BF16 as MIXED_B
                    STATUS_NAMES)
 
 __all__ = ["Net", "solve", "apply_laplacian", "apply_precond", "apply_precond_noalloc", "apply_precond_transpose", "asymmetry", "lanczos", "ritz_rhs", "NpsError", "SolveInfo", "Server",
-           "train_workspace", "net_forward", "net_backward", "train_loss", "Precond", "TrainLoss",
+           "train_workspace", "net_forward", "net_backward", "train_loss", "train_step", "Precond", "TrainLoss",
            "FP64", "FP32", "MIXED_BF16", "MIXED_FP16", "NPSDO", "PCG", "FPCG", "workspace", "vector_dtype"]
 
 
@@ -338,10 +338,19 @@ def _ws_args(ws: torch.Tensor):
     return _aligned(ws), ws.numel() - (_aligned(ws) - ws.data_ptr())
 
 
-def net_forward(net: Net, labels: torch.Tensor, r: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
-    """y = P(I, r); the activations stay in ws for net_backward."""
+def _train_precision(t: torch.Tensor, precision: int | None) -> int:
+    prec = (FP64 if t.dtype == torch.float64 else FP32) if precision is None else precision
+    if t.dtype != vector_dtype(prec):
+        raise ValueError(f"vectors must be {vector_dtype(prec)} for training precision {prec}")
+    return prec
+
+
+def net_forward(net: Net, labels: torch.Tensor, r: torch.Tensor, ws: torch.Tensor,
+                precision: int | None = None) -> torch.Tensor:
+    """y = P(I, r); the activations stay in ws for net_backward.  precision:
+    FP64, FP32 or MIXED_BF16 (default from r's dtype)."""
     _check_device(labels, r)
-    prec = FP64 if r.dtype == torch.float64 else FP32
+    prec = _train_precision(r, precision)
     y = torch.empty_like(r)
     wp, wb = _ws_args(ws)
     rc = _lib.nps_net_forward(net.handle, labels.data_ptr(), _dims(labels.shape), r.data_ptr(), y.data_ptr(), prec,
@@ -351,10 +360,11 @@ def net_forward(net: Net, labels: torch.Tensor, r: torch.Tensor, ws: torch.Tenso
     return y
 
 
-def train_loss(labels: torch.Tensor, b: torch.Tensor, y: torch.Tensor, levels: int, ws: torch.Tensor):
+def train_loss(labels: torch.Tensor, b: torch.Tensor, y: torch.Tensor, levels: int, ws: torch.Tensor,
+               precision: int | None = None):
     """(loss, dL/dy) of || b - A y ||_2."""
     _check_device(labels, b, y)
-    prec = FP64 if y.dtype == torch.float64 else FP32
+    prec = _train_precision(y, precision)
     gy = torch.empty_like(y)
     wp, wb = _ws_args(ws)
     rc, loss = _lib.nps_train_loss(labels.data_ptr(), _dims(labels.shape), levels, b.data_ptr(), y.data_ptr(),
@@ -365,10 +375,10 @@ def train_loss(labels: torch.Tensor, b: torch.Tensor, y: torch.Tensor, levels: i
 
 
 def net_backward(net: Net, labels: torch.Tensor, r: torch.Tensor, gy: torch.Tensor, grad: torch.Tensor,
-                 ws: torch.Tensor) -> torch.Tensor:
+                 ws: torch.Tensor, precision: int | None = None) -> torch.Tensor:
     """grad += dL/dparams (float64 device tensor of nps_param_count entries)."""
     _check_device(labels, r, gy, grad)
-    prec = FP64 if r.dtype == torch.float64 else FP32
+    prec = _train_precision(r, precision)
     wp, wb = _ws_args(ws)
     rc = _lib.nps_net_backward(net.handle, labels.data_ptr(), _dims(labels.shape), r.data_ptr(), gy.data_ptr(),
                                grad.data_ptr(), prec, wp, wb, _stream())
@@ -391,6 +401,23 @@ def _cached_net(params: torch.Tensor, levels: int, device) -> Net:
     net = Net(params.detach().cpu().numpy(), levels, device=device)
     _net_cache[0] = (weakref.ref(params), params._version, levels, str(device), net)
     return net
+
+
+def train_step(net: Net, labels: torch.Tensor, b: torch.Tensor, grad: torch.Tensor, ws: torch.Tensor,
+               precision: int | None = None) -> float:
+    """One step over a batch (nps_train_step): labels uint8 (B, nz, ny, nx),
+    b (B, nz, ny, nx) float64 / float32; grad += d(mean loss)/dparams; returns
+    the mean loss.  ws: train_workspace of one system."""
+    _check_device(labels, b, grad)
+    if labels.dim() != 4 or labels.shape != b.shape or labels.dtype != torch.uint8:
+        raise ValueError("labels (uint8) and b must both have shape (batch, nz, ny, nx)")
+    prec = _train_precision(b, precision)
+    wp, wb = _ws_args(ws)
+    rc, loss = _lib.nps_train_step(net.handle, labels.data_ptr(), _dims(labels.shape[1:]), labels.shape[0],
+                                   b.data_ptr(), grad.data_ptr(), prec, wp, wb, _stream())
+    if rc != _lib.NPS_OK:
+        raise NpsError(rc, "nps_train_step")
+    return loss
 
 
 class Precond(torch.autograd.Function):

@@ -104,6 +104,8 @@ _lib.nps_train_loss.argtypes = [_vp, nps_dims, _int, _vp, _vp, _vp, ctypes.POINT
 _lib.nps_train_loss.restype = _int
 _lib.nps_net_backward.argtypes = [_vp, _vp, nps_dims, _vp, _vp, _vp, _int, _vp, _sz, _vp]
 _lib.nps_net_backward.restype = _int
+_lib.nps_train_step.argtypes = [_vp, _vp, nps_dims, _int, _vp, _vp, ctypes.POINTER(ctypes.c_double), _int, _vp, _sz, _vp]
+_lib.nps_train_step.restype = _int
 _lib.nps_profile_enable.argtypes, _lib.nps_profile_enable.restype = [_int], _int
 _lib.nps_profile_read.argtypes = [ctypes.POINTER(nps_kernel_stat), _int, ctypes.POINTER(_int)]
 _lib.nps_profile_read.restype = _int
@@ -116,6 +118,7 @@ EXPORTED = ["nps_param_count", "nps_net_bytes", "nps_net_create", "nps_net_destr
             "nps_lanczos", "nps_ritz_workspace_bytes", "nps_ritz_rhs", "nps_server_create",
             "nps_server_destroy", "nps_server_request_bytes", "nps_server_submit", "nps_server_step",
             "nps_server_poll", "nps_train_workspace_bytes", "nps_net_forward", "nps_train_loss", "nps_net_backward",
+            "nps_train_step",
             "nps_profile_enable", "nps_profile_read", "nps_last_error"]
 NPS_PENDING = 2
 
@@ -265,6 +268,14 @@ def nps_train_loss(labels_d: int, dims: nps_dims, levels: int, b_d: int, y_d: in
 def nps_net_backward(net: int, labels_d: int, dims: nps_dims, r_d: int, gy_d: int, grad_d: int, precision: int,
                      ws_d: int, ws_bytes: int, stream: int) -> int:
     return _lib.nps_net_backward(net, labels_d, dims, r_d, gy_d, grad_d, precision, ws_d, ws_bytes, stream)
+
+
+def nps_train_step(net: int, labels_d: int, dims: nps_dims, batch: int, b_d: int, grad_d: int, precision: int,
+                   ws_d: int, ws_bytes: int, stream: int) -> tuple[int, float]:
+    loss = ctypes.c_double(0.0)
+    rc = _lib.nps_train_step(net, labels_d, dims, batch, b_d, grad_d, ctypes.byref(loss), precision, ws_d, ws_bytes,
+                             stream)
+    return rc, loss.value
 
 
 def nps_profile_enable(on: int) -> int:

@@ -37,6 +37,7 @@ struct nps_net {
     int levels = 0;
     char* dev = nullptr;
     size_t off_w64 = 0, off_w32 = 0, off_mfma = 0, off_aff = 0;
+    size_t off_wbf = 0, off_wbf32 = 0;   // count form with C and D rounded to bf16 (the bf16 training leg)
     double aff_b[2 * kMaxLevels] = {};   // Bbar of Aff_1^l, Aff_2^l (host copy)
 };
 
@@ -199,6 +200,7 @@ struct TrainLayout {
     size_t xup[kMaxLevels + 1], x2[kMaxLevels + 1];
     size_t gx[kMaxLevels + 1], gx1[kMaxLevels + 1], gr1[kMaxLevels + 1], gr2[kMaxLevels + 1];
     size_t wpart, spart, dc, res;
+    size_t y, gy, lacc;          // the batch step: network output, its loss gradient, the loss sum
     size_t dsym;                 // solve with P^T o P: the direction after P^T
     size_t total;
 };
@@ -232,6 +234,9 @@ TrainLayout make_train_layout(nps_dims d, int levels, int precision, bool solve 
     t.spart = put(sizeof(double) * 3 * kTaps * kSumBlocks * levels);
     t.dc = put(sizeof(double) * 2 * levels);
     t.res = put(s * ncells(level_grid(d, 1)));
+    t.y = put(s * ncells(level_grid(d, 1)));
+    t.gy = put(s * ncells(level_grid(d, 1)));
+    t.lacc = put(sizeof(double));
     if (solve) t.dsym = put(s * ncells(level_grid(d, 1)));
     t.total = off;
     return t;
@@ -345,11 +350,16 @@ int launch(const char* name, double cells, hipStream_t s, F&& f) {
     return NPS_OK;
 }
 
-size_t net_sizes(int levels, size_t* o64, size_t* o32, size_t* omf, size_t* oaff) {
+size_t net_sizes(int levels, size_t* o64, size_t* o32, size_t* omf, size_t* oaff, size_t* obf = nullptr,
+                 size_t* obf32 = nullptr) {
     const int nb = 2 * levels - 1;
     size_t off = 0;
     *o64 = off;
     off += align256(sizeof(CConvW<double>) * nb);
+    if (obf) *obf = off;
+    off += align256(sizeof(CConvW<double>) * nb);
+    if (obf32) *obf32 = off;
+    off += align256(sizeof(CConvW<float>) * nb);
     *o32 = off;
     off += align256(sizeof(CConvW<float>) * nb);
     *omf = off;
@@ -366,6 +376,12 @@ int block_up(const nps_net* net, int l) { return net->levels + l - 1; }
 template <class T>
 const CConvW<T>* cconv_block(const nps_net* net, int b) {
     const size_t off = sizeof(T) == 8 ? net->off_w64 : net->off_w32;
+    return reinterpret_cast<const CConvW<T>*>(net->dev + off) + b;
+}
+// The count form rounded to bf16 (values held as doubles or floats).
+template <class T>
+const CConvW<T>* cconv_block_bf16(const nps_net* net, int b) {
+    const size_t off = sizeof(T) == 8 ? net->off_wbf : net->off_wbf32;
     return reinterpret_cast<const CConvW<T>*>(net->dev + off) + b;
 }
 const MfmaW* mfma_block(const nps_net* net, int b) {
@@ -453,7 +469,7 @@ uint32_t full_count(int l) { return 1u << (3 * (l - 1)); }
 // Image pyramid as counts, Aff scalars, and the stored kernels of small levels.
 template <class T>
 int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay,
-              void* ws, hipStream_t s) {
+              void* ws, hipStream_t s, bool bf16w = false) {
     const int L = net->levels;
     State* st = mptr<State>(ws, lay.state);
     double* partials = mptr<double>(ws, lay.partials);
@@ -522,7 +538,8 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
         const int grid = elem_grid((per_cell ? 1 : (size_t)kTaps) * ncells(g));
         for (int which = 0; which < (l < L ? 2 : 1); ++which) {
             T* out = mptr<T>(ws, which == 0 ? lay.k1[l] : lay.k2[l]);
-            const CConvW<double>* w = cconv_block<double>(net, which == 0 ? block_down(l) : block_up(net, l));
+            const int blk = which == 0 ? block_down(l) : block_up(net, l);
+            const CConvW<double>* w = bf16w ? cconv_block_bf16<double>(net, blk) : cconv_block<double>(net, blk);
             auto go = [&](auto l1, auto tg) {
                 constexpr bool L1 = decltype(l1)::value;
                 constexpr int TG = decltype(tg)::value;
@@ -654,12 +671,12 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
 // Level-1 down kernel: x1 = CConv_1(r), r^2 = Pool(x1), r the network input.
 template <class T>
 int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan& plan, const Layout& lay, void* ws,
-                const T* r, hipStream_t s) {
+                const T* r, hipStream_t s, bool bf16w = false) {
     const Grid g = level_grid(d, 1);
     State* st = mptr<State>(ws, lay.state);
     T* x1 = mptr<T>(ws, lay.x1[1]);
     T* rnext = mptr<T>(ws, lay.rb[2]);
-    const CConvW<T>* w = cconv_block<T>(net, block_down(1));
+    const CConvW<T>* w = bf16w ? cconv_block_bf16<T>(net, block_down(1)) : cconv_block<T>(net, block_down(1));
     const MfmaW* wm = mfma_block(net, block_down(1));
     const T* kst = plan.km[1] == kStored ? cptr<T>(ws, lay.k1[1]) : nullptr;
     return with_kmode<T>(plan.km[1], [&](auto km) {
@@ -1327,13 +1344,14 @@ size_t off_aff(int L, int l) { return (size_t)(2 * L - 1) * (27 * 81 + 27) + (si
 
 template <class T>
 int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws,
-                  const T* r, T* y, hipStream_t s) {
+                  const T* r, T* y, hipStream_t s, bool bf16w = false) {
     const int L = net->levels;
     const Layout& lay = tl.base;
     const Plan plan = make_plan(d, L, vec_bytes(NPS_FP32) == sizeof(T) ? NPS_FP32 : NPS_FP64, true);
     State* st = mptr<State>(ws, lay.state);
+    auto wblock = [&](int b) { return bf16w ? cconv_block_bf16<T>(net, b) : cconv_block<T>(net, b); };
     NPS_TRY(launch("state_init", 0, s, [&] { k_state_init<<<1, 64, 0, s>>>(st, 0, 0, 0, 0, 0); }));
-    NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s));
+    NPS_TRY(run_setup<T>(net, labels, d, plan, lay, ws, s, bf16w));
     auto img = [&](int l) -> const void* {
         return l == 1 ? static_cast<const void*>(labels) : static_cast<const void*>(cptr<uint32_t>(ws, lay.counts[l]));
     };
@@ -1346,7 +1364,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         else
             NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<false><<<kSumBlocks, kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
     }
-    NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s));
+    NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s, bf16w));
     for (int l = 2; l <= L; ++l) {
         const Grid g = level_grid(d, l);
         const int grid = tile_grid(g);
@@ -1355,7 +1373,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         T* x1 = mptr<T>(ws, lay.x1[l]);
         T* rnext = l < L ? mptr<T>(ws, lay.rb[l + 1]) : nullptr;
         const T* kst = cptr<T>(ws, lay.k1[l]);
-        const CConvW<T>* w = cconv_block<T>(net, block_down(l));
+        const CConvW<T>* w = wblock(block_down(l));
         if (l < L)
             NPS_TRY(launch("net_down", (double)ncells(g), s, [&] {
                 k_down<T, kStored, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, nullptr, kst, st,
@@ -1377,7 +1395,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         T* xo = mptr<T>(ws, tl.xup[l]);
         T* x2o = mptr<T>(ws, tl.x2[l]);
         const T* kst = cptr<T>(ws, lay.k2[l]);
-        const CConvW<T>* w = cconv_block<T>(net, block_up(net, l));
+        const CConvW<T>* w = wblock(block_up(net, l));
         NPS_TRY(launch("net_up", (double)ncells(g), s, [&] {
             k_up<T, kStored><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, nullptr, kst, l - 1, st, x2o,
                                                          nullptr);
@@ -1390,7 +1408,7 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         const T* x1 = cptr<T>(ws, lay.x1[1]);
         T* x2o = mptr<T>(ws, tl.x2[1]);
         const T* kst = cptr<T>(ws, lay.k2[1]);
-        const CConvW<T>* w = cconv_block<T>(net, block_up(net, 1));
+        const CConvW<T>* w = wblock(block_up(net, 1));
         double* partials = mptr<double>(ws, lay.partials);
         NPS_TRY(launch("net_up_l1", (double)ncells(g), s, [&] {
             k_up_l1<T, kStored, true><<<grid, kBlock, 0, s>>>(labels, g, xc, x1, y, w, nullptr, kst, st, partials, nullptr,
@@ -1410,7 +1428,7 @@ int wgrad_reduce(double* wpart, int nparts, double scale, double* gW, double* dc
     });
 }
 
-template <class T>
+template <class T, int WP = std::is_same<T, float>::value ? kWgMfma32 : kWgVector>
 int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* ws,
                    const T* r, const T* gy, double* grad, hipStream_t s) {
     const int L = net->levels;
@@ -1435,11 +1453,11 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
         T* gr2 = mptr<T>(ws, tl.gr2[l]);
         if (l == 1)
             NPS_TRY(launch("train_bwd_up", (double)ncells(g), s, [&] {
-                k_bwd_up<T, true, true><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
+                k_bwd_up<T, true, true, WP><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
             }));
         else
             NPS_TRY(launch("train_bwd_up", (double)ncells(g), s, [&] {
-                k_bwd_up<T, false, true><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
+                k_bwd_up<T, false, true, WP><<<grid, kBlock, 0, s>>>(img(l), g, gin, xc, x1, x2, k2, st, l - 1, gx1, gr2, wpart);
             }));
         const double scale = std::ldexp(1.0, -3 * (l - 1));
         double* gW = grad + off_c2(L, l);
@@ -1466,11 +1484,11 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
         T* gr1 = l > 1 ? mptr<T>(ws, tl.gr1[l]) : nullptr;
         if (l == 1)
             NPS_TRY(launch("train_bwd_down", (double)ncells(g), s, [&] {
-                k_bwd_down<T, true, true><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
+                k_bwd_down<T, true, true, WP><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
             }));
         else
             NPS_TRY(launch("train_bwd_down", (double)ncells(g), s, [&] {
-                k_bwd_down<T, false, true><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
+                k_bwd_down<T, false, true, WP><<<grid, kBlock, 0, s>>>(img(l), g, gx1, gr_next, r1, k1, gr1, wpart);
             }));
         const double scale = std::ldexp(1.0, -3 * (l - 1));
         double* gW = grad + off_c1(l);
@@ -1495,13 +1513,57 @@ int train_loss(const uint8_t* labels, nps_dims d, const TrainLayout& tl, void* w
     NPS_TRY(launch("control", 0, s, [&] {
         k_control<kStageLoss><<<1, kCtlBlock, 0, s>>>(st, partials, grid, 0, 0, 0, 0, 0.0, 0.0, 0.0, nullptr);
     }));
-    NPS_TRY(launch("train_gy", (double)ncells(g), s, [&] { k_train_gy<T><<<grid, kBlock, 0, s>>>(labels, g, res, st, gy); }));
+    NPS_TRY(launch("train_gy", (double)ncells(g), s, [&] { k_train_gy<T><<<grid, kBlock, 0, s>>>(labels, g, res, st, gy, 1.0); }));
     double rr = 0.0;
     NPS_HIP(hipMemcpyAsync(&rr, &st->rr, sizeof(double), hipMemcpyDeviceToHost, s));
     NPS_HIP(hipStreamSynchronize(s));
     *loss_h = std::sqrt(rr);
     return NPS_OK;
 }
+
+// One step over a batch (the mean loss of Sec. "Training"): the systems run
+// one after another in the same workspace, each forward keeping its per-level
+// activations for its own backward; the loss gradient of each is weighed by
+// 1/batch, so the backward passes add the gradient of the mean.
+template <class T, int WP>
+int train_step(const nps_net* net, const uint8_t* labels, nps_dims d, int batch, const T* b, double* grad,
+               double* loss_h, const TrainLayout& tl, void* ws, hipStream_t s, bool bf16w) {
+    const Layout& lay = tl.base;
+    const Grid g = level_grid(d, 1);
+    const size_t n = ncells(g);
+    State* st = mptr<State>(ws, lay.state);
+    double* partials = mptr<double>(ws, lay.partials);
+    T* res = mptr<T>(ws, tl.res);
+    T* y = mptr<T>(ws, tl.y);
+    T* gy = mptr<T>(ws, tl.gy);
+    double* lacc = mptr<double>(ws, tl.lacc);
+    const double w = 1.0 / batch;
+    const int grid = tile_grid(g);
+    NPS_TRY(launch("train_loss_sum", 0, s, [&] { k_loss_accumulate<<<1, 1, 0, s>>>(st, lacc, 0.0, 1); }));
+    for (int i = 0; i < batch; ++i) {
+        const uint8_t* lab = labels + (size_t)i * n;
+        const T* bi = b + (size_t)i * n;
+        NPS_TRY(train_forward<T>(net, lab, d, tl, ws, bi, y, s, bf16w));
+        NPS_TRY(launch("train_residual", (double)n, s, [&] {
+            k_train_residual<T><<<grid, kBlock, 0, s>>>(lab, g, bi, y, res, partials);
+        }));
+        NPS_TRY(launch("control", 0, s, [&] {
+            k_control<kStageLoss><<<1, kCtlBlock, 0, s>>>(st, partials, grid, 0, 0, 0, 0, 0.0, 0.0, 0.0, nullptr);
+        }));
+        NPS_TRY(launch("train_gy", (double)n, s, [&] { k_train_gy<T><<<grid, kBlock, 0, s>>>(lab, g, res, st, gy, w); }));
+        NPS_TRY(launch("train_loss_sum", 0, s, [&] { k_loss_accumulate<<<1, 1, 0, s>>>(st, lacc, w, 0); }));
+        NPS_TRY((train_backward<T, WP>(net, lab, d, tl, ws, bi, gy, grad, s)));
+    }
+    NPS_HIP(hipMemcpyAsync(loss_h, lacc, sizeof(double), hipMemcpyDeviceToHost, s));
+    NPS_HIP(hipStreamSynchronize(s));
+    return NPS_OK;
+}
+
+// Training precisions: NPS_FP64 (double vectors, vector-ALU parameter sums),
+// NPS_FP32 (float vectors, fp32 matrix-core sums), NPS_MIXED_BF16 (float
+// vectors, kernels from bf16-rounded weights, bf16 matrix-core sums with fp32
+// accumulation).
+bool train_precision_ok(int p) { return p == NPS_FP64 || p == NPS_FP32 || p == NPS_MIXED_BF16; }
 
 }  // namespace
 
@@ -1563,8 +1625,8 @@ int nps_net_create(const double* params_h, size_t n_params, int levels, void* de
     if (n_params != nps_param_count(levels))
         return fail(NPS_EINVAL, "blob has %zu parameters, expected %zu", n_params, nps_param_count(levels));
     if (reinterpret_cast<uintptr_t>(dev_buf_d) % 256) return fail(NPS_EINVAL, "device buffer not 256-byte aligned");
-    size_t o64, o32, omf, oaff;
-    const size_t need = net_sizes(levels, &o64, &o32, &omf, &oaff);
+    size_t o64, o32, omf, oaff, obf, obf32;
+    const size_t need = net_sizes(levels, &o64, &o32, &omf, &oaff, &obf, &obf32);
     if (dev_bytes < need) return fail(NPS_ENOMEM, "device buffer has %zu bytes, needs %zu", dev_bytes, need);
     for (size_t i = 0; i < n_params; ++i)
         if (!std::isfinite(params_h[i])) return fail(NPS_ENONFINITE, "parameter %zu is not finite", i);
@@ -1575,6 +1637,8 @@ int nps_net_create(const double* params_h, size_t n_params, int levels, void* de
     auto* w32 = reinterpret_cast<CConvW<float>*>(host.data() + o32);
     auto* wmf = reinterpret_cast<MfmaW*>(host.data() + omf);
     auto* aff = reinterpret_cast<AffW*>(host.data() + oaff);
+    auto* wbf = reinterpret_cast<CConvW<double>*>(host.data() + obf);
+    auto* wbf32 = reinterpret_cast<CConvW<float>*>(host.data() + obf32);
     nps_net* net = new nps_net();
     const double* p = params_h;
     const size_t cw = 27 * 81, cb = 27;
@@ -1606,6 +1670,30 @@ int nps_net_create(const double* params_h, size_t n_params, int levels, void* de
         for (int c = 0; c < 3; ++c)
             for (int i = 0; i < kTaps; ++i) t.Kpure[c][i] = (float)s.Kpure[c][i];
         to_mfma(s, wmf[b]);
+        // bf16-rounded count form: the single bf16 piece the mixed path's matrix
+        // cores use; the pure-window kernels follow from the rounded values
+        CConvW<double>& r = wbf[b];
+        const int lvl = b < levels ? b + 1 : b - levels + 1;
+        const double full = std::ldexp(1.0, 3 * (lvl - 1));
+        for (int t = 0; t < kTaps; ++t) {
+            r.C[t] = bf16_value(bf16_rne((float)s.C[t]));
+            double kf = r.C[t], ka = r.C[t];
+            for (int o = 0; o < kTaps; ++o)
+                for (int c = 0; c < 2; ++c) {
+                    r.D[o][t][c] = bf16_value(bf16_rne((float)s.D[o][t][c]));
+                    (c == 0 ? kf : ka) += r.D[o][t][c] * full;
+                }
+            r.Kpure[kFluid][t] = kf;
+            r.Kpure[kAir][t] = ka;
+            r.Kpure[kSolid][t] = r.C[t];
+        }
+        CConvW<float>& r32 = wbf32[b];
+        for (int i = 0; i < kTaps; ++i) r32.C[i] = (float)r.C[i];
+        for (int o = 0; o < kTaps; ++o)
+            for (int i = 0; i < kTaps; ++i)
+                for (int c = 0; c < 2; ++c) r32.D[o][i][c] = (float)r.D[o][i][c];
+        for (int c = 0; c < 3; ++c)
+            for (int i = 0; i < kTaps; ++i) r32.Kpure[c][i] = (float)r.Kpure[c][i];
     }
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e = hipMemcpyAsync(dev_buf_d, host.data(), need, hipMemcpyHostToDevice, s);
@@ -1620,6 +1708,8 @@ int nps_net_create(const double* params_h, size_t n_params, int levels, void* de
     net->off_w32 = o32;
     net->off_mfma = omf;
     net->off_aff = oaff;
+    net->off_wbf = obf;
+    net->off_wbf32 = obf32;
     *out = net;
     return NPS_OK;
 }
@@ -1723,7 +1813,7 @@ int nps_apply_precond_noalloc(const nps_net* net, const uint8_t* labels_d, nps_d
 
 size_t nps_train_workspace_bytes(nps_dims dims, int levels, int precision) {
     if (check_dims(dims, levels) != NPS_OK) return 0;
-    if (precision != NPS_FP64 && precision != NPS_FP32) return 0;
+    if (!train_precision_ok(precision)) return 0;
     return make_train_layout(dims, levels, precision).total;
 }
 
@@ -1731,36 +1821,60 @@ int nps_net_forward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, 
                     int precision, void* ws_d, size_t ws_bytes, void* stream) {
     if (!net || !labels_d || !r_d || !y_d || !ws_d) return fail(NPS_EINVAL, "null argument");
     NPS_TRY(check_dims(dims, net->levels));
-    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "training precision must be FP64 or FP32");
+    if (!train_precision_ok(precision)) return fail(NPS_EINVAL, "training precision must be FP64, FP32 or MIXED_BF16");
     const TrainLayout tl = make_train_layout(dims, net->levels, precision);
     if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
     if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == NPS_FP64)
         return train_forward<double>(net, labels_d, dims, tl, ws_d, static_cast<const double*>(r_d), static_cast<double*>(y_d), s);
-    return train_forward<float>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(r_d), static_cast<float*>(y_d), s);
+    return train_forward<float>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(r_d), static_cast<float*>(y_d), s,
+                                precision == NPS_MIXED_BF16);
 }
 
 int nps_net_backward(const nps_net* net, const uint8_t* labels_d, nps_dims dims, const void* r_d, const void* gy_d,
                      double* grad_d, int precision, void* ws_d, size_t ws_bytes, void* stream) {
     if (!net || !labels_d || !r_d || !gy_d || !grad_d || !ws_d) return fail(NPS_EINVAL, "null argument");
     NPS_TRY(check_dims(dims, net->levels));
-    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "training precision must be FP64 or FP32");
+    if (!train_precision_ok(precision)) return fail(NPS_EINVAL, "training precision must be FP64, FP32 or MIXED_BF16");
     const TrainLayout tl = make_train_layout(dims, net->levels, precision);
     if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (precision == NPS_FP64)
         return train_backward<double>(net, labels_d, dims, tl, ws_d, static_cast<const double*>(r_d),
                                       static_cast<const double*>(gy_d), grad_d, s);
+    if (precision == NPS_MIXED_BF16)
+        return train_backward<float, kWgMfmaBf16>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(r_d),
+                                                  static_cast<const float*>(gy_d), grad_d, s);
     return train_backward<float>(net, labels_d, dims, tl, ws_d, static_cast<const float*>(r_d),
                                  static_cast<const float*>(gy_d), grad_d, s);
+}
+
+int nps_train_step(const nps_net* net, const uint8_t* labels_d, nps_dims dims, int batch, const void* b_d,
+                   double* grad_d, double* loss_h, int precision, void* ws_d, size_t ws_bytes, void* stream) {
+    if (!net || !labels_d || !b_d || !grad_d || !loss_h || !ws_d) return fail(NPS_EINVAL, "null argument");
+    if (batch < 1) return fail(NPS_EINVAL, "batch must be at least 1");
+    NPS_TRY(check_dims(dims, net->levels));
+    if (!train_precision_ok(precision)) return fail(NPS_EINVAL, "training precision must be FP64, FP32 or MIXED_BF16");
+    const TrainLayout tl = make_train_layout(dims, net->levels, precision);
+    if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
+    if (reinterpret_cast<uintptr_t>(ws_d) % 256) return fail(NPS_EINVAL, "workspace not 256-byte aligned");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (precision == NPS_FP64)
+        return train_step<double, kWgVector>(net, labels_d, dims, batch, static_cast<const double*>(b_d), grad_d, loss_h,
+                                             tl, ws_d, s, false);
+    if (precision == NPS_MIXED_BF16)
+        return train_step<float, kWgMfmaBf16>(net, labels_d, dims, batch, static_cast<const float*>(b_d), grad_d, loss_h,
+                                              tl, ws_d, s, true);
+    return train_step<float, kWgMfma32>(net, labels_d, dims, batch, static_cast<const float*>(b_d), grad_d, loss_h, tl,
+                                        ws_d, s, false);
 }
 
 int nps_train_loss(const uint8_t* labels_d, nps_dims dims, int levels, const void* b_d, const void* y_d, void* gy_d,
                    double* loss_h, int precision, void* ws_d, size_t ws_bytes, void* stream) {
     if (!labels_d || !b_d || !y_d || !gy_d || !loss_h || !ws_d) return fail(NPS_EINVAL, "null argument");
     NPS_TRY(check_dims(dims, levels));
-    if (precision != NPS_FP64 && precision != NPS_FP32) return fail(NPS_EINVAL, "training precision must be FP64 or FP32");
+    if (!train_precision_ok(precision)) return fail(NPS_EINVAL, "training precision must be FP64, FP32 or MIXED_BF16");
     const TrainLayout tl = make_train_layout(dims, levels, precision);
     if (ws_bytes < tl.total) return fail(NPS_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, tl.total);
     hipStream_t s = static_cast<hipStream_t>(stream);

@@ -1655,6 +1655,7 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         const bool col = xx < g.nx && yy < g.ny;
         const LD below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
         auto pre = plane(x0, y0, z0);
+        auto pre2 = plane(x0, y0, z0 + 1);
         if (first) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
             if (done) return;
@@ -1686,7 +1687,7 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         T dm = direction(below);   // own column, plane s - 2
         uint32_t lm = below.l;
         T rv = T(0);               // r of plane s - 1
-        for (int s = z0; s <= z1; ++s) {
+        auto step = [&](int s, auto& pre) {
             const int cur = s & 1, prev = cur ^ 1;
             __syncthreads();   // the reads of this buffer (plane s - 2) are done
             put_batch(pre, [&](int i, LD e) {
@@ -1694,7 +1695,7 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
                 lab_s[cur][i] = e.l;
             });
             const T rnext = r[col && s < z1 ? cell_index(g, s, yy, xx) : 0];
-            if (s < z1) pre = plane(x0, y0, s + 1);
+            if (s + 2 <= z1) pre = plane(x0, y0, s + 2);
             __syncthreads();   // plane s is staged
             if (s > z0) {      // the own cell of plane s - 1
                 const T dv = d_s[prev][own];
@@ -1725,6 +1726,11 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
                 lm = lc;
             }
             rv = rnext;
+        };
+        // planes are loaded two steps ahead of their staging
+        for (int s = z0; s <= z1; s += 2) {
+            step(s, pre);
+            if (s + 1 <= z1) step(s + 1, pre2);
         }
     }
     block_partials<kBlock>(v, partials);
@@ -1780,6 +1786,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         const bool col = xx < g.nx && yy < g.ny;
         const XDL<X, T> below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
         auto pre = plane(x0, y0, z0);
+        auto pre2 = plane(x0, y0, z0 + 1);
         if (first) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
             if (done) return;
@@ -1801,7 +1808,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         X xm = updated(below);   // own column, plane s - 2
         uint32_t lm = below.l;
         double bv = 0.0;         // b of plane s - 1
-        for (int s = z0; s <= z1; ++s) {
+        auto step = [&](int s, auto& pre) {
             const int cur = s & 1, prev = cur ^ 1;
             __syncthreads();   // the reads of this buffer (plane s - 2) are done
             put_batch(pre, [&](int i, XDL<X, T> e) {
@@ -1809,7 +1816,7 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
                 x_s[cur][i] = updated(e);
             });
             const double bnext = b[col && s < z1 ? cell_index(g, s, yy, xx) : 0];
-            if (s < z1) pre = plane(x0, y0, s + 1);
+            if (s + 2 <= z1) pre = plane(x0, y0, s + 2);
             __syncthreads();   // plane s is staged
             if (s > z0) {      // the own cell of plane c = s - 1
                 const uint32_t lc = lab_s[prev][own];
@@ -1840,6 +1847,11 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
                 lm = lc;
             }
             bv = bnext;
+        };
+        // planes are loaded two steps ahead of their staging
+        for (int s = z0; s <= z1; s += 2) {
+            step(s, pre);
+            if (s + 1 <= z1) step(s + 1, pre2);
         }
     }
     if (!first || !done) block_partials<kBlock>(v, partials);

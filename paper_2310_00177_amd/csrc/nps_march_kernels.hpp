@@ -140,11 +140,14 @@ __device__ __forceinline__ float march_group(const uint2* ring, const int (&pb)[
     uint2 rv[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) rv[j] = ring[pb[j] + c.lofs[j] + q * PHX];
-    float part = 0.0f;
+    float pa = 0.0f, pb2 = 0.0f;   // two chains of four
     if (mode == kGPure) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) part = fmaf(c.kp[j], fbits(rv[j].x), part);
-        return part;
+        for (int j = 0; j < 4; ++j) {
+            pa = fmaf(c.kp[j], fbits(rv[j].x), pa);
+            pb2 = fmaf(c.kp[j + 4], fbits(rv[j + 4].x), pb2);
+        }
+        return pa + pb2;
     }
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     u16x8 B[2];
@@ -167,8 +170,11 @@ __device__ __forceinline__ float march_group(const uint2* ring, const int (&pb)[
             }
     }
 #pragma unroll
-    for (int j = 0; j < 8; ++j) part = fmaf(acc[j >> 2][j & 3], fbits(rv[j].x), part);
-    return part;
+    for (int j = 0; j < 4; ++j) {
+        pa = fmaf(acc[0][j], fbits(rv[j].x), pa);
+        pb2 = fmaf(acc[1][j], fbits(rv[j + 4].x), pb2);
+    }
+    return pa + pb2;
 }
 
 // Sum of a value over the lane pairs (l, l ^ 32) and (l, l ^ 16), given per
@@ -206,6 +212,28 @@ __device__ __forceinline__ uint2 march_record(float r, uint8_t l) {
     return uint2{bits(l == kFluid ? r : 0.0f), feat_word<KM, true>(l)};
 }
 
+// The staged elements of a thread in a footprint's plane (element i = thread
+// + k kBlock, clamped to the last one): offset y nx + x inside a plane and
+// whether the column lies in the grid.  Formed once per footprint; a plane's
+// loads then only add its z offset.
+struct StageElems {
+    static constexpr int K = (kPlane + kBlock - 1) / kBlock;
+    uint32_t off[K];
+    bool in[K];
+};
+
+__device__ __forceinline__ StageElems stage_elems(Grid g, int x0, int y0) {
+    StageElems e;
+#pragma unroll
+    for (int k = 0; k < StageElems::K; ++k) {
+        const int i = min((int)threadIdx.x + k * kBlock, kPlane - 1);
+        const int yy = y0 + i / PHX - 1, xx = x0 + i % PHX - 1;
+        e.in[k] = yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx;
+        e.off[k] = e.in[k] ? (uint32_t)yy * g.nx + xx : 0u;
+    }
+    return e;
+}
+
 struct RLab {   // CConv input and label of one staged cell
     float r;
     uint8_t l;
@@ -229,13 +257,19 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
     const Grid gc = coarser(g);
     const int lane = threadIdx.x & 63, gq = lane >> 4, n = lane & 15;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    auto plane = [&](int x0, int y0, int zz) {
-        return load_batch<kPlane, RLab>([&](int i) {
-            const int yy = y0 + i / PHX - 1, xx = x0 + i % PHX - 1;
-            const bool in = in_grid(g, zz, yy, xx);
-            const size_t q = in ? cell_index(g, zz, yy, xx) : 0;
-            return RLab{*at_or(r, q, in, pad_zero<float>()), *at_or(lab, q, in, g_pad_solid)};
-        });
+    const uint32_t pstride = (uint32_t)g.ny * (uint32_t)g.nx;
+    StageElems se;
+    auto plane = [&](int zz) {
+        Batch<kPlane, RLab> bt;
+        const bool zin = zz >= 0 && zz < g.nz;
+        const uint32_t base = zin ? (uint32_t)zz * pstride : 0u;
+#pragma unroll
+        for (int k = 0; k < StageElems::K; ++k) {
+            const bool in = zin && se.in[k];
+            const size_t q = base + se.off[k];
+            bt.v[k] = RLab{*at_or(r, q, in, pad_zero<float>()), *at_or(lab, q, in, g_pad_solid)};
+        }
+        return bt;
     };
     bool first = true;
     for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
@@ -246,9 +280,11 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         const bool col = xx < g.nx && yy < g.ny;
         const uint32_t* mrow = gmode + ((size_t)cy * cl.ncx + cx) * 4 + wv;   // + z * ncy * ncx * 4 words
         const size_t mstride = (size_t)cl.ncy * cl.ncx * 4;
+        const uint32_t own_off = col ? (uint32_t)yy * g.nx + xx : 0u;
+        se = stage_elems(g, x0, y0);
         // planes are loaded two steps ahead of their staging
-        auto preA = plane(x0, y0, z0 - 1);
-        auto preB = plane(x0, y0, z0);
+        auto preA = plane(z0 - 1);
+        auto preB = plane(z0);
         if (first) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
             if (done) return;
@@ -259,13 +295,13 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         auto step = [&](int s, auto& pre) {
             uint2* buf = ring + (s & 3) * kPlaneP;
             put_batch(pre, [&](int i, RLab e) { buf[i] = march_record<KM>(e.r, e.l); });
-            if (s + 2 <= z1) pre = plane(x0, y0, s + 2);
+            if (s + 2 <= z1) pre = plane(s + 2);
             const int c = s - 1;
             const uint32_t modes = c >= z0 ? __builtin_amdgcn_readfirstlane(mrow[(size_t)c * mstride]) : 0u;
             __syncthreads();   // plane s is staged
             if (c < z0) return;
             const float out = march_cconv<KM>(ring, c, modes, mc);
-            if (col) x1[cell_index(g, c, yy, xx)] = out;
+            if (col) x1[(size_t)c * pstride + own_off] = out;
             // 2x2x2 pool: x pair (DPP quad_perm [1,0,3,2]), y pair (rows 2k, 2k+1)
             const float px = out + fbits(__builtin_amdgcn_update_dpp(0u, bits(out), 0xB1, 0xF, 0xF, false));
             const auto t = __builtin_amdgcn_permlane16_swap(bits(px), bits(px), false, false);
@@ -326,27 +362,35 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
     const float* adp[kMaxOrtho] = {ad0, ad1, ad2, ad3};
     const uint32_t fluid_word = feat_word<KM, true>(kFluid);
     double v[kRedWidth] = {0.0, 0.0, 0.0, 0.0};
+    const uint32_t pstride = (uint32_t)g.ny * (uint32_t)g.nx, cstride = (uint32_t)gc.ny * (uint32_t)gc.nx;
+    StageElems se;
+    // per staged element: its four coarse cells (rows ly, lyn x columns lx, lxn of
+    // the staged coarse block, one byte each), formed once per footprint
+    uint32_t ipos[StageElems::K];
+    uint32_t coff = 0;   // the thread's coarse cell (jy, jx) of the staged block, clamped
     // staged element i of a plane: fine (y0 - 1 + i / PHX, x0 - 1 + i % PHX)
-    auto labels = [&](int x0, int y0, int zz) {
-        return load_batch<kPlane, uint8_t>([&](int i) {
-            const int yy = y0 + i / PHX - 1, xx = x0 + i % PHX - 1;
-            const bool in = in_grid(g, zz, yy, xx);
-            return *at_or(lab, in ? cell_index(g, zz, yy, xx) : 0, in, g_pad_solid);
-        });
+    auto labels = [&](int zz) {
+        Batch<kPlane, uint8_t> bt;
+        const bool zin = zz >= 0 && zz < g.nz;
+        const uint32_t base = zin ? (uint32_t)zz * pstride : 0u;
+#pragma unroll
+        for (int k = 0; k < StageElems::K; ++k) {
+            const bool in = zin && se.in[k];
+            bt.v[k] = *at_or(lab, (size_t)base + se.off[k], in, g_pad_solid);
+        }
+        return bt;
     };
-    // coarse plane m (clamped) of the footprint: cells (cy0 + i / kCX, cx0 + i % kCX), clamped
-    auto coarse = [&](int x0, int y0, int m) {
-        const int i = min((int)threadIdx.x, kCPlane - 1);
-        const int jz = min(max(m, 0), gc.nz - 1), jy = min(max(y0 / 2 - 1 + i / kCX, 0), gc.ny - 1),
-                  jx = min(max(x0 / 2 - 1 + i % kCX, 0), gc.nx - 1);
-        return xc[cell_index(gc, jz, jy, jx)];
+    // coarse plane m (clamped) of the footprint
+    auto coarse = [&](int m) {
+        const int jz = min(max(m, 0), gc.nz - 1);
+        return xc[(size_t)jz * cstride + coff];
     };
     auto put_coarse = [&](int m, float val) {
         if (threadIdx.x < kCPlane) csh[(m + 3) % 3][threadIdx.x] = val;
     };
     // the lane cell's operands of output plane zz (an unused dot slot reads x1)
-    auto cell_ops = [&](int zz, int yy, int xx, bool col) {
-        const size_t q = col ? cell_index(g, zz, yy, xx) : 0;
+    auto cell_ops = [&](int zz, uint32_t own_off) {
+        const size_t q = (size_t)zz * pstride + own_off;
         UpCell<ND> u;
         u.x1 = x1[q];
 #pragma unroll
@@ -361,15 +405,34 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
         const bool col = xx < g.nx && yy < g.ny;
         const int own = (gq + 1) * PHX + 16 * wv + n + 1;
+        const uint32_t own_off = col ? (uint32_t)yy * g.nx + xx : 0u;
         const uint32_t* mrow = gmode + ((size_t)cy * cl.ncx + cx) * 4 + wv;
         const size_t mstride = (size_t)cl.ncy * cl.ncx * 4;
         const int m0 = z0 / 2;
+        se = stage_elems(g, x0, y0);
+        {
+            const int i = min((int)threadIdx.x, kCPlane - 1);
+            const int jy = min(max(y0 / 2 - 1 + i / kCX, 0), gc.ny - 1), jx = min(max(x0 / 2 - 1 + i % kCX, 0), gc.nx - 1);
+            coff = (uint32_t)jy * gc.nx + jx;
+        }
+#pragma unroll
+        for (int k = 0; k < StageElems::K; ++k) {
+            // along each axis the own coarse cell f >> 1 (weight 3/4) and its
+            // neighbour on f's side (1/4), as indices into the staged block
+            const int i = min((int)threadIdx.x + k * kBlock, kPlane - 1);
+            const int fy = y0 + i / PHX - 1, fx = x0 + i % PHX - 1;
+            const int ly = (fy >> 1) - (y0 / 2 - 1), lyn = (fy & 1) ? ly + 1 : ly - 1;
+            const int lx = (fx >> 1) - (x0 / 2 - 1), lxn = (fx & 1) ? lx + 1 : lx - 1;
+            ipos[k] = se.in[k] ? (uint32_t)(ly * kCX + lx) | (uint32_t)(ly * kCX + lxn) << 8 |
+                                     (uint32_t)(lyn * kCX + lx) << 16 | (uint32_t)(lyn * kCX + lxn) << 24
+                               : 0u;
+        }
         // loads run two steps ahead: fine-plane labels, the coarse plane the
         // next even step writes, the cell operands of the plane a step computes
-        const float cm0 = coarse(x0, y0, m0 - 1), cm1 = coarse(x0, y0, m0);
-        float cpre = coarse(x0, y0, m0 + 1);
-        auto lA = labels(x0, y0, z0 - 1);
-        auto lB = labels(x0, y0, z0);
+        const float cm0 = coarse(m0 - 1), cm1 = coarse(m0);
+        float cpre = coarse(m0 + 1);
+        auto lA = labels(z0 - 1);
+        auto lB = labels(z0);
         UpCell<ND> oA, oB;
         if (first) {
             __asm__ volatile("" ::: "memory");
@@ -387,32 +450,30 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
             const int jz = s >> 1, jzn = (s & 1) ? jz + 1 : jz - 1;   // virtual planes, clamped when staged
             const float* cz0 = csh[(jz + 3) % 3];
             const float* cz1 = csh[(jzn + 3) % 3];
-            put_batch(lpre, [&](int i, uint8_t l) {
-                const int hy = i / PHX, hx = i % PHX;
-                const int fy = y0 + hy - 1, fx = x0 + hx - 1;
+#pragma unroll
+            for (int k = 0; k < StageElems::K; ++k) {
+                const int i = threadIdx.x + k * kBlock;
                 float val = 0.0f;
-                if (i < kPlane && zin && fy >= 0 && fy < g.ny && fx >= 0 && fx < g.nx) {
-                    // along each axis the own coarse cell f >> 1 (weight 3/4) and its
-                    // neighbour on f's side (1/4), as indices into the staged block
-                    const int ly = (fy >> 1) - (y0 / 2 - 1), lyn = (fy & 1) ? ly + 1 : ly - 1;
-                    const int lx = (fx >> 1) - (x0 / 2 - 1), lxn = (fx & 1) ? lx + 1 : lx - 1;
+                if (zin && se.in[k] && i < kPlane) {
+                    const uint32_t w = ipos[k];
+                    const int a00 = w & 255, a01 = (w >> 8) & 255, a10 = (w >> 16) & 255, a11 = w >> 24;
                     auto bil = [&](const float* p) {
-                        const float a = fmaf(0.25f, p[ly * kCX + lxn] - p[ly * kCX + lx], p[ly * kCX + lx]);
-                        const float b = fmaf(0.25f, p[lyn * kCX + lxn] - p[lyn * kCX + lx], p[lyn * kCX + lx]);
+                        const float a = fmaf(0.25f, p[a01] - p[a00], p[a00]);
+                        const float b = fmaf(0.25f, p[a11] - p[a10], p[a10]);
                         return fmaf(0.25f, b - a, a);
                     };
                     const float v0 = bil(cz0), v1 = bil(cz1);
                     val = fmaf(0.25f, v1 - v0, v0);
                 }
                 // the CConv_2 input is not masked (only the level's output is)
-                buf[i] = uint2{bits(val), feat_word<KM, true>(l)};
-            });
+                buf[i] = uint2{bits(val), feat_word<KM, true>(lpre.v[k])};
+            }
             // an even step writes coarse plane (s >> 1) + 1, which the odd fine plane s + 1 needs
             if (!(s & 1) && s < z1) {
                 put_coarse((s >> 1) + 1, cpre);
-                if (s + 2 < z1) cpre = coarse(x0, y0, (s >> 1) + 2);
+                if (s + 2 < z1) cpre = coarse((s >> 1) + 2);
             }
-            if (s + 2 <= z1) lpre = labels(x0, y0, s + 2);
+            if (s + 2 <= z1) lpre = labels(s + 2);
             const int c = s - 1;
             const uint32_t modes = c >= z0 ? __builtin_amdgcn_readfirstlane(mrow[(size_t)c * mstride]) : 0u;
             __syncthreads();   // plane s (and the coarse plane) staged
@@ -421,13 +482,13 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
                 const bool fl = ring[(c & 3) * kPlaneP + own].y == fluid_word;
                 const float out = fl ? (c1 * ops.x1 + c2 * x2) * scale : 0.0f;
                 if (col) {
-                    dhat[cell_index(g, c, yy, xx)] = out;
+                    dhat[(size_t)c * pstride + own_off] = out;
 #pragma unroll
                     for (int j = 0; j < ND; ++j)
                         if (j < ndots) v[j] = fma((double)out, (double)ops.ad[j], v[j]);
                 }
             }
-            if (s + 1 < z1) ops = cell_ops(s + 1, yy, xx, col);   // plane s + 1, formed at step s + 2
+            if (s + 1 < z1) ops = cell_ops(s + 1, own_off);   // plane s + 1, formed at step s + 2
         };
         // z1 - z0 is even, so the steps z0 - 1 .. z1 come in pairs
         for (int s = z0 - 1; s <= z1; s += 2) {

@@ -15,6 +15,8 @@
 
 #include "nps_kernels.hpp"
 
+#include <type_traits>
+
 namespace nps {
 
 constexpr int kFeat = 2 * kTaps + 1;            // 54 counts + the constant
@@ -52,8 +54,133 @@ __device__ __forceinline__ void accumulate_wgrad(const T* u_s, const uint32_t* i
     }
 }
 
+// Float: the tile's contribution as a matrix product on the matrix cores,
+// sums[t][f] += sum_p U[t][p] F[f][p] with U[t][p] = g(p) r(p + a_t) (from
+// u_s) and F[f][p] the f-th count feature of cell p (f = 2 o + c: count of
+// channel c at window position o; f = 54 the constant 1), contracted over the
+// tile's 256 cells four at a time on v_mfma_f32_16x16x4_f32 (exact fp32
+// products, fp32 accumulation).  Wave w owns the feature block f = 16 w ..
+// 16 w + 15 and both tap blocks; lane (k, n) supplies U[16 mb + n][p0 + k]
+// and F[16 w + n][p0 + k].  acc[mb][i] ends as sums[16 mb + 4 k + i][16 w + n].
+template <bool L1>
+__device__ __forceinline__ void accumulate_wgrad_mfma(const float* u_s, const uint32_t* img_s, f32x4 (&acc)[2]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = lane & 15, k = lane >> 4;
+    const int f = 16 * wv + n, o = min(f >> 1, kTaps - 1), ch = f & 1;
+    const int off = halo_off_rt(o);
+    for (int p0 = 0; p0 < kBlock; p0 += 4) {
+        const int p = p0 + k;
+        const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+        float b;
+        if (f < 2 * kTaps) {
+            uint32_t n0, n1;
+            counts_of<L1>(img_s[halo_base(lx, ly, lz) + off], n0, n1);
+            b = (float)(ch ? n1 : n0);
+        } else {
+            b = f == 2 * kTaps ? 1.0f : 0.0f;
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            const int t = 16 * mb + n;
+            const float a = t < kTaps ? u_s[t * kUStride + p] : 0.0f;
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[mb], 0, 0, 0);
+        }
+    }
+}
+
+// The same product with bf16 operands and fp32 accumulation (the bf16
+// training leg): v_mfma_f32_16x16x32_bf16 contracts 32 cells at a time, lane
+// (k, n) supplying U and F at cells p0 + 8 k .. p0 + 8 k + 7 (U rounded to
+// nearest even; the counts are small integers, exact).
+__device__ __forceinline__ uint16_t bf16_bits_rne(float v) {
+    uint32_t u = __float_as_uint(v);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <bool L1>
+__device__ __forceinline__ void accumulate_wgrad_bf16(const float* u_s, const uint32_t* img_s, f32x4 (&acc)[2]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = lane & 15, k = lane >> 4;
+    const int f = 16 * wv + n, o = min(f >> 1, kTaps - 1), ch = f & 1;
+    const int off = halo_off_rt(o);
+    for (int p0 = 0; p0 < kBlock; p0 += 32) {
+        u16x8 b, a[2];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int p = p0 + 8 * k + j;
+            const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
+            float fv;
+            if (f < 2 * kTaps) {
+                uint32_t n0, n1;
+                counts_of<L1>(img_s[halo_base(lx, ly, lz) + off], n0, n1);
+                fv = (float)(ch ? n1 : n0);
+            } else {
+                fv = f == 2 * kTaps ? 1.0f : 0.0f;
+            }
+            b[j] = bf16_bits_rne(fv);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) {
+                const int t = 16 * mb + n;
+                a[mb][j] = bf16_bits_rne(t < kTaps ? u_s[t * kUStride + p] : 0.0f);
+            }
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+            acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[mb]),
+                                                              __builtin_bit_cast(bf16x8, b), acc[mb], 0, 0, 0);
+    }
+}
+
+__device__ __forceinline__ void write_wgrad_partial_mfma(const f32x4 (&acc)[2], double* part, double gc1, double gc2) {
+    double* mine = part + (size_t)blockIdx.x * kWPart;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int n = lane & 15, k = lane >> 4, f = 16 * wv + n;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 16 * mb + 4 * k + i;
+            if (t < kTaps && f < kFeat) mine[t * kFeat + f] = (double)acc[mb][i];
+        }
+    if (threadIdx.x == 0) {
+        mine[kWGrad] = gc1;
+        mine[kWGrad + 1] = gc2;
+        mine[kWGrad + 2] = 0.0;
+    }
+}
+
+// How the parameter sums are contracted: per-thread sums on the vector ALU
+// (double), fp32 matrix cores (float), bf16 matrix cores with fp32
+// accumulation (the bf16 training leg).
+enum WgradPath : int { kWgVector = 0, kWgMfma32 = 1, kWgMfmaBf16 = 2 };
+
+// Per-block accumulator of a CConv block's parameter sums.
+template <class T, int WP = std::is_same<T, float>::value ? kWgMfma32 : kWgVector>
+struct WgradAcc {
+    static constexpr bool kMfma = WP != kWgVector;
+    static_assert(!kMfma || std::is_same<T, float>::value, "matrix-core sums are float");
+    T v[kMfma ? 1 : (kWGrad + kBlock - 1) / kBlock];
+    f32x4 m[kMfma ? 2 : 1];
+    __device__ __forceinline__ void init() {
+        if constexpr (kMfma) {
+            m[0] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            m[1] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        } else {
+#pragma unroll
+            for (int j = 0; j < (kWGrad + kBlock - 1) / kBlock; ++j) v[j] = T(0);
+        }
+    }
+    template <bool L1>
+    __device__ __forceinline__ void add(const T* u_s, const uint32_t* img_s) {
+        if constexpr (WP == kWgMfmaBf16) accumulate_wgrad_bf16<L1>(u_s, img_s, m);
+        else if constexpr (WP == kWgMfma32) accumulate_wgrad_mfma<L1>(u_s, img_s, m);
+        else accumulate_wgrad<T, L1>(u_s, img_s, v);
+    }
+};
+
 template <class T>
-__device__ __forceinline__ void write_wgrad_partial(const T (&acc)[(kWGrad + kBlock - 1) / kBlock], double* part,
+__device__ __forceinline__ void write_wgrad_partial_vec(const T (&acc)[(kWGrad + kBlock - 1) / kBlock], double* part,
                                            double gc1, double gc2) {
     constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
     double* mine = part + (size_t)blockIdx.x * kWPart;
@@ -69,13 +196,19 @@ __device__ __forceinline__ void write_wgrad_partial(const T (&acc)[(kWGrad + kBl
     }
 }
 
+template <class T, int WP>
+__device__ __forceinline__ void write_wgrad_partial(const WgradAcc<T, WP>& a, double* part, double gc1, double gc2) {
+    if constexpr (WgradAcc<T, WP>::kMfma) write_wgrad_partial_mfma(a.m, part, gc1, gc2);
+    else write_wgrad_partial_vec<T>(a.v, part, gc1, gc2);
+}
+
 // Backward of one up block at level l:  x = c1 x1 + c2 CConv_2(Interp(xc)).
 // Given gx = dL/dx: writes gx1 = c1 gx (the x1 share), gr2 = CConv_2^T(c2 gx),
 // and (WGRAD) a partial of the CConv_2 parameter sums and of dL/dc1 = gx.x1,
 // dL/dc2 = gx.x2.  Level 1 (L1): gx is masked to fluid first.  Without
 // WGRAD this is the up block's part of the adjoint P^T (xc, x1, x2 and part
 // are not read).
-template <class T, bool L1, bool WGRAD>
+template <class T, bool L1, bool WGRAD, int WP = std::is_same<T, float>::value ? kWgMfma32 : kWgVector>
 __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img, Grid g, const T* __restrict__ gx_in,
                                                    const T* __restrict__ xc, const T* __restrict__ x1,
                                                    const T* __restrict__ x2, const T* __restrict__ k2, const State* st,
@@ -86,10 +219,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
     __shared__ T g_s[kHaloP];       // gx (masked at level 1); the block's output gradient is c2 gx
     __shared__ T c_s[WGRAD ? kCoarseTileP : 1];
     __shared__ T u_s[WGRAD ? kTaps * kUStride : 1];
-    constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
-    T acc[NO];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) acc[j] = T(0);
+    WgradAcc<T, WP> acc;
+    acc.init();
     double gc1 = 0.0, gc2 = 0.0;
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
@@ -135,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
         }
         if constexpr (WGRAD) {
             __syncthreads();
-            accumulate_wgrad<T, L1>(u_s, img_s, acc);
+            acc.template add<L1>(u_s, img_s);
         }
     }
     if constexpr (!WGRAD) return;
@@ -155,7 +286,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
         b1 += sh[0][i];
         b2 += sh[1][i];
     }
-    write_wgrad_partial<T>(acc, part, b1, b2);
+    write_wgrad_partial(acc, part, b1, b2);
 }
 
 // Backward of one down block at level l:  x1 = CConv_1(r1).  The output
@@ -165,7 +296,7 @@ __global__ __launch_bounds__(kBlock) void k_bwd_up(const void* __restrict__ img,
 // where the input was) and (WGRAD) a partial of the parameter sums.
 // Without WGRAD this is the down block's part of the adjoint P^T (r1 and
 // part are not read).
-template <class T, bool L1, bool WGRAD>
+template <class T, bool L1, bool WGRAD, int WP = std::is_same<T, float>::value ? kWgMfma32 : kWgVector>
 __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ img, Grid g, const T* __restrict__ gx1,
                                                      const T* __restrict__ gr_next, const T* __restrict__ r1,
                                                      const T* __restrict__ k1, T* __restrict__ gr1, double* part) {
@@ -173,10 +304,8 @@ __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ im
     __shared__ T r_s[WGRAD ? kHaloP : 1];
     __shared__ T g_s[kHaloP];
     __shared__ T u_s[WGRAD ? kTaps * kUStride : 1];
-    constexpr int NO = (kWGrad + kBlock - 1) / kBlock;
-    T acc[NO];
-#pragma unroll
-    for (int j = 0; j < NO; ++j) acc[j] = T(0);
+    WgradAcc<T, WP> acc;
+    acc.init();
     const Tiles tl = tiles_of(g);
     const size_t n = ncells(g);
     const Grid gc = coarser(g);
@@ -220,10 +349,10 @@ __global__ __launch_bounds__(kBlock) void k_bwd_down(const void* __restrict__ im
         }
         if constexpr (WGRAD) {
             __syncthreads();
-            accumulate_wgrad<T, L1>(u_s, img_s, acc);
+            acc.template add<L1>(u_s, img_s);
         }
     }
-    if constexpr (WGRAD) write_wgrad_partial<T>(acc, part, 0.0, 0.0);
+    if constexpr (WGRAD) write_wgrad_partial(acc, part, 0.0, 0.0);
 }
 
 // Adjoint of the 2x trilinear upsampling: gc(j) = sum over fine cells f of
@@ -424,13 +553,14 @@ __global__ __launch_bounds__(kBlock) void k_train_residual(const uint8_t* __rest
     block_partials<kBlock>(v, partials);
 }
 
-// dL/dy = -A res / ||res|| (A is symmetric), from the residual and its norm in st->rr.
+// dL/dy = -w A res / ||res|| (A is symmetric), from the residual and its
+// norm in st->rr; w weighs the system in a batch mean (1 alone).
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_train_gy(const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ res,
-                                                     const State* st, T* __restrict__ gy) {
+                                                     const State* st, T* __restrict__ gy, double w) {
     __shared__ uint32_t lab_s[kHaloP];
     __shared__ T r_s[kHaloP];
-    const T inv = (T)(-1.0 / sqrt(st->rr));
+    const T inv = (T)(-w / sqrt(st->rr));
     const Tiles tl = tiles_of(g);
     const int lx = threadIdx.x % TX, ly = (threadIdx.x / TX) % TY, lz = threadIdx.x / (TX * TY);
     const int base = halo_base(lx, ly, lz);
@@ -447,6 +577,12 @@ __global__ __launch_bounds__(kBlock) void k_train_gy(const uint8_t* __restrict__
         const int xx = o.x0 + lx, yy = o.y0 + ly, zz = o.z0 + lz;
         if (in_grid(g, zz, yy, xx)) gy[cell_index(g, zz, yy, xx)] = inv * apply_A<T, T, uint32_t>(lab_s, r_s, base, HX, HX * HY);
     }
+}
+
+// acc = 0 (set) or acc += w ||res|| of the system just evaluated (one thread).
+__global__ void k_loss_accumulate(const State* st, double* acc, double w, int set) {
+    const double v = w * sqrt(st->rr);
+    *acc = set ? 0.0 : *acc + v;
 }
 
 }  // namespace nps
