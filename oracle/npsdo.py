@@ -55,7 +55,7 @@ def solve(labels: np.ndarray, b: np.ndarray, precond, tol: float = 1e-6,
         0.5 * _dot(x, A(x)) - _dot(b, x)]}
     if bnorm == 0.0:
         return SolveResult(np.zeros(labels.shape), 0, OK, 0.0, hist)
-    D, AD = [], []          # D[i-1] = d_i, AD[i-1] = A d_i
+    D, AD = {}, {}          # D[i] = d_i, AD[i] = A d_i for the last n_ortho directions
     k = 0
     status = OK
     while True:
@@ -69,7 +69,7 @@ def solve(labels: np.ndarray, b: np.ndarray, precond, tol: float = 1e-6,
         d = precond(r / rnorm)
         betas = []
         for i in range(max(1, k - n_ortho), k):       # k - n_ortho <= i < k, i >= 1
-            di, adi = D[i - 1], AD[i - 1]
+            di, adi = D[i], AD[i]
             beta = _dot(d, adi) / _dot(di, adi)
             d = d - beta * di
             betas.append(beta)
@@ -82,8 +82,9 @@ def solve(labels: np.ndarray, b: np.ndarray, precond, tol: float = 1e-6,
         alpha = _dot(r, d) / dAd
         x = x + alpha * d
         r = b - A(x)
-        D.append(d)
-        AD.append(Ad)
+        D[k], AD[k] = d, Ad
+        D.pop(k - n_ortho, None)                       # no longer in any window
+        AD.pop(k - n_ortho, None)
         hist["rnorm"].append(float(np.linalg.norm(r)))
         hist["alpha"].append(alpha)
         hist["beta"].append(betas)
