@@ -79,7 +79,7 @@ def parse():
     ap.add_argument("--serving", action="store_true",
                     help="run the request-server sweep instead (Poisson arrivals, mixed grid sizes)")
     ap.add_argument("--requests", type=int, default=512)
-    ap.add_argument("--qps", type=float, nargs="+", default=[20.0, 50.0, 100.0])
+    ap.add_argument("--qps", type=float, nargs="+", default=[20.0, 50.0, 100.0, 200.0, 400.0])
     ap.add_argument("--slots", type=int, default=16)
     return ap.parse_args()
 
@@ -139,73 +139,97 @@ def cpu_baseline(labels, b, params, iters_sample):
                       f"{ref['iterations']}-iteration solve of this workload"}
 
 
+def _serving_request(i):
+    """Request i of the serving workload: grid N ~ U{64, 96, 128, 160} (seed
+    10000 + i), labels of the 128^3 recipe scaled by N/128 (seed 10000 + i),
+    N(0,1) right-hand side on fluid (seed 20000 + i)."""
+    import nps_inputs as gi
+    n = [64, 96, 128, 160][int(np.random.default_rng(10000 + i).integers(0, 4))]
+    lab = gi.gen_labels(gi.scene_serving(n), seed=10000 + i)
+    return n, lab, gi.gen_rhs(lab, seed=20000 + i)
+
+
 def serving_sweep(args):
     """Continuous-batching server: `requests` solves with Poisson arrivals at each
-    QPS, grids drawn uniformly from {64,96,128,160}^3, tol 1e-6, mixed bf16."""
+    QPS (seed 77), each request its own seeded grid drawn from {64,96,128,160}^3,
+    tol 1e-6, mixed bf16; the offered rates run past the server's capacity,
+    whose served rate is the headline.  Back-to-back single solves of the same
+    requests give the reference rate in cell-iterations/s."""
+    import multiprocessing as mp
+
     import torch
 
     import nps_inputs as gi
     import paper_2310_00177_amd as nps
 
+    with mp.get_context("fork").Pool(8) as pool:
+        reqs = pool.map(_serving_request, range(args.requests))
+    print(f"# serving: {len(reqs)} requests ready", file=sys.stderr, flush=True)
     torch.cuda.set_device(0)
-    sizes = [64, 96, 128, 160]
     net = nps.Net(gi.multilevel_params(6), 6)
-    # a pool of distinct scenes (4 per size) and right-hand sides (2 per scene), reused cyclically
-    pool = []
-    for n in sizes:
-        for j in range(4):
-            lab = gi.gen_labels(gi.scene_serving(n), seed=10000 + 10 * n + j)
-            for k in range(2):
-                pool.append((n, lab, gi.gen_rhs(lab, seed=20000 + 10 * n + 2 * j + k)))
-    print(f"# serving: pool of {len(pool)} requests ready", file=sys.stderr, flush=True)
+    # reference: back-to-back single solves of the first 64 requests
+    ref_cells_its, t_ref = 0.0, 0.0
+    for n, lab, b in reqs[:64]:
+        labels_d, b_d = torch.from_numpy(lab).cuda(), torch.from_numpy(b).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = nps.solve(net, labels_d, b_d, tol=1e-6, precision=nps.MIXED_BF16)
+        t_ref += time.perf_counter() - t0
+        ref_cells_its += float(lab.size) * info.iterations
+    ref_rate = ref_cells_its / t_ref
+    print(f"# single solves back to back: {ref_rate / 1e9:.2f} G cell-iterations/s", file=sys.stderr, flush=True)
     rng = np.random.default_rng(77)
     results = []
     for qps in args.qps:
         srv = nps.Server(net, hbm_budget=64 << 30, max_slots=args.slots)
-        picks = [pool[i] for i in rng.integers(0, len(pool), size=args.requests)]
         gaps = rng.exponential(1.0 / qps, size=args.requests)
         arrivals = np.cumsum(gaps) - gaps[0]
-        # warm-up: one request of each size
-        for n in sizes:
-            lab, b = next((p[1], p[2]) for p in pool if p[0] == n)
+        for n, lab, b in reqs[:4]:   # warm-up
             rid = srv.submit(lab, b)
             while srv.poll(rid) is None:
                 srv.step()
-        lat, its, ok, inflight, peak = [], [], 0, {}, 0
+        lat, its, ok, inflight, peak, cells_its = [], [], 0, {}, 0, 0.0
         t0 = time.perf_counter()
         i = 0
         t_end = t0
         while len(lat) < args.requests:
             now = time.perf_counter() - t0
             while i < args.requests and arrivals[i] <= now:
-                n, lab, b = picks[i]
-                inflight[srv.submit(lab, b)] = n
+                n, lab, b = reqs[i]
+                inflight[srv.submit(lab, b)] = lab.size
                 i += 1
             active, queued = srv.step()
             peak = max(peak, active)
-            for rid in list(inflight):
+            # admission is first in, first out, so every request on the device or
+            # finished is among the oldest slots + a few in flight: polling those
+            # keeps the host loop short when many requests wait
+            for rid in list(inflight)[:2 * args.slots]:
                 r = srv.poll(rid)
                 if r is not None:
                     x, info, ms = r
                     lat.append(ms)
                     its.append(info.iterations)
+                    cells_its += float(inflight[rid]) * info.iterations
                     ok += info.status == 0 and info.rel_residual < 1e-6
                     del inflight[rid]
                     t_end = time.perf_counter()
         wall = t_end - t0
         srv.close()
         lat = np.array(lat)
-        row = {"qps": qps, "throughput": args.requests / wall, "p50_ms": float(np.percentile(lat, 50)),
-               "p99_ms": float(np.percentile(lat, 99)), "mean_iterations": float(np.mean(its)),
-               "converged": int(ok), "peak_active": int(peak)}
-        print(f"# serving qps {qps}: {row}", file=sys.stderr, flush=True)
+        row = {"qps": qps, "throughput": args.requests / wall,
+               "cell_iterations_per_s": cells_its / wall, "vs_single_solves": cells_its / wall / ref_rate,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_iterations": float(np.mean(its)), "converged": int(ok), "peak_active": int(peak)}
+        print(f"# serving qps {row['qps']}: {row}", file=sys.stderr, flush=True)
         results.append(row)
+    sat = max(results, key=lambda r: r["throughput"])   # offered rates past capacity: the served rate
     out = {"metric": "served solves/sec to 1e-6 rel. residual, grids {64,96,128,160}^3; p50/p99 latency",
-           "value": max(r["throughput"] for r in results), "unit": "solves/s", "n_gpus": 1,
+           "value": sat["throughput"], "unit": "solves/s", "n_gpus": 1,
            "higher_is_better": True, "dtype": "bf16+f32+f64", "data": "synthetic",
-           "config": {"workload": f"{args.requests} requests per QPS, Poisson arrivals, grids uniform in "
-                                  f"{{64,96,128,160}}^3 from a pool of 16 scenes x 2 RHS, tol 1e-6, L=6, "
-                                  f"n_ortho=2, mixed bf16, {args.slots} slots", "weights": "multilevel"},
+           "config": {"workload": f"{args.requests} requests per QPS, Poisson arrivals (seed 77), request i: grid "
+                                  "N ~ U{64,96,128,160} and labels seed 10000+i, N(0,1) RHS seed 20000+i, tol 1e-6, "
+                                  f"L=6, n_ortho=2, mixed bf16, {args.slots} slots", "weights": "multilevel",
+                      "single_solve_cell_iterations_per_s": ref_rate},
            "sweep": results}
     print(json.dumps(out))
 

@@ -191,11 +191,14 @@ int nps_apply_precond_noalloc(const nps_net* net, const uint8_t* labels_d, nps_d
  * Request server: continuous batching of solves of different grids.
  *
  * The server owns one device arena (hbm_budget bytes, allocated once by
- * nps_server_create) and up to max_slots streams.  nps_server_submit copies
- * a request's labels and b into server-owned pinned host memory and queues
- * it (first in, first out).  nps_server_step never blocks: it admits queued
- * requests while the arena has room for their footprint
- * (nps_server_request_bytes) and a slot is free, and advances every admitted
+ * nps_server_create) and up to max_slots streams.  nps_server_submit queues
+ * a request (first in, first out) without copying it: labels_h and b_h are
+ * borrowed and must stay valid and unchanged until nps_server_poll has
+ * returned the request's result or the server is destroyed.  nps_server_step
+ * never blocks: it admits queued requests while the arena has room for their
+ * footprint (nps_server_request_bytes) and a slot is free (admission copies
+ * the request's inputs into a pinned staging buffer, reused across requests
+ * of one size, and sends them on the slot's stream), and advances every admitted
  * request by at most one NPSDO iteration on its own stream, so iterations of
  * different requests overlap on the device.  A finished request leaves its
  * slot and its arena space at once; nps_server_poll returns NPS_PENDING (2)

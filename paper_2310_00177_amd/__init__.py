@@ -266,10 +266,11 @@ def ritz_rhs(V: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, coef: tor
 class Server:
     """Continuous-batching request server (nps_server_* in the C ABI).
 
-    submit() copies a request's host arrays and queues it; step() admits
-    requests by HBM footprint and advances every admitted one by at most one
-    iteration on its own stream; poll() returns (x, info, latency_ms) once a
-    request has finished, else None.
+    submit() queues a request (the server keeps a reference to its host
+    arrays, which must not be modified until the request is polled); step()
+    admits requests by HBM footprint and advances every admitted one by at most
+    one iteration on its own stream; poll() returns (x, info, latency_ms) once
+    a request has finished, else None.
     """
 
     def __init__(self, net: Net, hbm_budget: int, max_slots: int = 8):
@@ -278,7 +279,7 @@ class Server:
         if rc != _lib.NPS_OK:
             raise NpsError(rc, "nps_server_create")
         self.handle = h
-        self._shapes = {}
+        self._held = {}   # request id -> the host arrays the library reads at admission
 
     def request_bytes(self, shape, tol=1e-6, max_iter=1000, n_ortho=2, precision=MIXED_BF16, method=0) -> int:
         opts = _lib.nps_opts(tol, max_iter, n_ortho, precision, 0, method, 0)
@@ -294,7 +295,7 @@ class Server:
         rc, rid = _lib.nps_server_submit(self.handle, lab.ctypes.data, _dims(lab.shape), bb.ctypes.data, opts)
         if rc != _lib.NPS_OK:
             raise NpsError(rc, "nps_server_submit")
-        self._shapes[rid] = lab.shape
+        self._held[rid] = (lab, bb)
         return rid
 
     def step(self) -> tuple:
@@ -304,13 +305,12 @@ class Server:
         return active, queued
 
     def poll(self, rid: int):
-        shape = self._shapes[rid]
-        x = np.empty(shape, dtype=np.float64)
+        x = np.empty(self._held[rid][0].shape, dtype=np.float64)
         info = _lib.nps_info()
         rc, lat = _lib.nps_server_poll(self.handle, rid, x.ctypes.data, info)
         if rc == _lib.NPS_PENDING:
             return None
-        del self._shapes[rid]
+        del self._held[rid]
         if rc < 0 and rc != _lib.NPS_EBREAKDOWN:
             x = None   # rejected before its solve ran: no solution
         return x, SolveInfo(info.iterations, rc, info.rel_residual, info.rel_residual_rec, info.refinements,
@@ -321,6 +321,7 @@ class Server:
         if h:
             _lib.nps_server_destroy(h)
             self.handle = None
+        self._held = {}
 
     def __del__(self):
         self.close()

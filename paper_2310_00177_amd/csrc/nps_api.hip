@@ -1104,7 +1104,9 @@ int precond_impl(const nps_net* net, const uint8_t* labels, nps_dims d, const T*
 // ---------------------------------------------------------------------------
 // request server
 // ---------------------------------------------------------------------------
-// Pinned host buffers reused by exact size (request grids repeat).
+// Pinned host buffers reused by exact size (request grids repeat).  Only
+// admitted and finished-but-unpolled requests hold one, so the pinned
+// footprint stays near max_slots requests however long the queue grows.
 struct PinnedPool {
     std::multimap<size_t, void*> free_;
     void* get(size_t bytes) {
@@ -1168,9 +1170,11 @@ struct Request {
     nps_dims d{};
     nps_opts o{};
     size_t n = 0;
-    uint8_t* lab_h = nullptr;   // pinned copies of the inputs
+    const uint8_t* lab_u = nullptr;   // the caller's inputs, read once at admission
+    const double* b_u = nullptr;
+    uint8_t* lab_h = nullptr;   // pinned staging of the inputs (admission to validation)
     double* b_h = nullptr;
-    double* x_h = nullptr;      // pinned result
+    double* x_h = nullptr;      // pinned result (from the finalize step until polled)
     bool x_ready = false;       // x_h was written (the request reached its finalize step)
     Phase phase = kQueued;
     int status = NPS_OK;
@@ -1244,6 +1248,20 @@ void retire(nps_server* srv, Slot& sl, int status) {
 }
 
 int admit(nps_server* srv, Slot& sl, Request* r) {
+    r->lab_h = static_cast<uint8_t*>(srv->pool.get(r->n));
+    r->b_h = static_cast<double*>(srv->pool.get(8 * r->n));
+    if (!r->lab_h || !r->b_h) {   // nothing enqueued yet: the request ends here
+        release_inputs(srv, r);
+        srv->arena.release(r->off, r->bytes);
+        r->status = fail(NPS_EDEVICE, "pinned host allocation failed");
+        r->t_done = Clock::now();
+        r->phase = Request::kDone;
+        return NPS_OK;
+    }
+    std::memcpy(r->lab_h, r->lab_u, r->n);
+    std::memcpy(r->b_h, r->b_u, 8 * r->n);
+    r->lab_u = nullptr;
+    r->b_u = nullptr;
     const RequestLayout rl = request_layout(r->d, srv->net->levels, r->o);
     char* base = srv->arena_d + r->off;
     Solver* sv = make_solver(r->o.precision);
@@ -1276,6 +1294,12 @@ int enqueue_finish(nps_server* srv, Slot& sl) {
     Request* r = sl.req;
     const RequestLayout rl = request_layout(r->d, srv->net->levels, r->o);
     double* x_d = reinterpret_cast<double*>(srv->arena_d + r->off + rl.x);
+    r->x_h = static_cast<double*>(srv->pool.get(8 * r->n));
+    if (!r->x_h) {   // let the slot's stream drain before its arena region is reused
+        NPS_HIP(hipStreamSynchronize(sl.s));
+        retire(srv, sl, fail(NPS_EDEVICE, "pinned host allocation failed"));
+        return NPS_OK;
+    }
     NPS_TRY(sl.sv->enqueue_finalize(x_d));
     NPS_HIP(hipMemcpyAsync(r->x_h, x_d, 8 * r->n, hipMemcpyDeviceToHost, sl.s));
     NPS_HIP(hipEventRecord(sl.ev[0], sl.s));
@@ -2242,18 +2266,8 @@ int nps_server_submit(nps_server* srv, const uint8_t* labels_h, nps_dims dims, c
     r->o = *opts;
     r->n = ncells(level_grid(dims, 1));
     r->bytes = bytes;
-    r->lab_h = static_cast<uint8_t*>(srv->pool.get(r->n));
-    r->b_h = static_cast<double*>(srv->pool.get(8 * r->n));
-    r->x_h = static_cast<double*>(srv->pool.get(8 * r->n));
-    if (!r->lab_h || !r->b_h || !r->x_h) {
-        srv->pool.put(r->n, r->lab_h);
-        srv->pool.put(8 * r->n, r->b_h);
-        srv->pool.put(8 * r->n, r->x_h);
-        delete r;
-        return fail(NPS_EDEVICE, "pinned host allocation failed");
-    }
-    std::memcpy(r->lab_h, labels_h, r->n);
-    std::memcpy(r->b_h, b_h, 8 * r->n);
+    r->lab_u = labels_h;
+    r->b_u = b_h;
     r->t_submit = Clock::now();
     srv->queue.push_back(r);
     srv->live[r->id] = r;
