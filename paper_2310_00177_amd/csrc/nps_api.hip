@@ -682,7 +682,7 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
         if constexpr (is_mfma(KM)) {
-            const int grid = persist_grid_n(&k_down_l1m<KM>, columns_of(g).count());
+            const int grid = persist_grid_n(&k_down_l1m<KM>, march_columns(g).count() / 2);
             return launch("net_down_l1", (double)ncells(g), s, [&] {
                 k_down_l1m<KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, st,
                                                        cptr<uint32_t>(ws, lay.gmode[0]));
@@ -716,7 +716,7 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
             auto go = [&](auto nd) {
                 constexpr int ND = decltype(nd)::value;
                 constexpr bool H = HOOK;
-                const int grid = persist_grid_n(&k_up_l1m<KM, H, H ? 0 : ND>, columns_of(g).count());
+                const int grid = persist_grid_n(&k_up_l1m<KM, H, H ? 0 : ND>, march_columns(g).count() / 2);
                 if (nparts) *nparts = grid;
                 return launch("net_up_l1", (double)ncells(g), s, [&] {
                     k_up_l1m<KM, H, H ? 0 : ND><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, st, partials,

@@ -33,6 +33,19 @@ namespace nps {
 
 enum GroupMode : uint32_t { kGZero = 0, kGPure = 1, kGGeneral = 2 };
 
+// Work items of the marching network kernels: a 64 x 4 column footprint
+// over a chunk of 4 z-planes (2 on grids with fewer than 1024 such items).
+// Shorter items than the 7-point kernels' keep the per-block work even: an
+// item's cost depends on its group modes (interface footprints cost up to
+// 1.7x empty ones), and block b takes items b, b + G, b + 2G, ... so each
+// block meets a spread of them.  A function of the grid alone: launches and
+// kernels agree on it.
+__host__ __device__ inline Columns march_columns(Grid g) {
+    const int ncx = (g.nx + PX - 1) / PX, ncy = (g.ny + PY - 1) / PY;
+    const int chunk = ncx * ncy * ((g.nz + 3) / 4) >= 1024 ? 4 : 2;
+    return Columns{ncx, ncy, (g.nz + chunk - 1) / chunk, chunk};
+}
+
 // One mode byte per (footprint, z, wave, row): index ((z ncy + cy) ncx + cx)
 // * 16 + 4 w + q, so a wave's four modes are one aligned word.
 __host__ __device__ inline size_t group_mode_bytes(Grid g) {
@@ -253,7 +266,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
     __shared__ uint2 ring[4 * kPlaneP];
     const int done = st->done;   // tested once the first loads are out
     const MarchCtx<KM> mc = march_ctx<KM>(wm, w);
-    const Columns cl = columns_of(g);
+    const Columns cl = march_columns(g);
     const Grid gc = coarser(g);
     const int lane = threadIdx.x & 63, gq = lane >> 4, n = lane & 15;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -272,8 +285,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         return bt;
     };
     bool first = true;
-    for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int wk = sp.t0;
+    for (int wk = blockIdx.x; wk < cl.count(); wk += gridDim.x) {
         const int cx = wk % cl.ncx, cy = (wk / cl.ncx) % cl.ncy, z0 = (wk / (cl.ncx * cl.ncy)) * cl.chunk;
         const int x0 = cx * PX, y0 = cy * PY, z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
@@ -355,7 +367,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
     const float scale = HOOK ? 1.0f : (float)st->scale;
     const int ndots = HOOK || st->sym ? 0 : min(st->ndots, ND);   // the symmetric variant dots after P^T
     const MarchCtx<KM> mc = march_ctx<KM>(wm, w);
-    const Columns cl = columns_of(g);
+    const Columns cl = march_columns(g);
     const Grid gc = coarser(g);
     const int lane = threadIdx.x & 63, gq = lane >> 4, n = lane & 15;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -398,8 +410,7 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         return u;
     };
     bool first = true;
-    for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int wk = sp.t0;
+    for (int wk = blockIdx.x; wk < cl.count(); wk += gridDim.x) {
         const int cx = wk % cl.ncx, cy = (wk / cl.ncx) % cl.ncy, z0 = (wk / (cl.ncx * cl.ncy)) * cl.chunk;
         const int x0 = cx * PX, y0 = cy * PY, z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
