@@ -582,6 +582,10 @@ int with_kmode(int km, F&& f) {
 template <class T>
 int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& lay, void* ws, hipStream_t s,
                const T** x2, const double* res_partials = nullptr, int res_np = 0, HostFlags* hf = nullptr) {
+    static const char* const kDownName[kMaxLevels + 1] = {"", "", "net_down_l2", "net_down_l3", "net_down_l4",
+                                                          "net_down_l5", "net_down_l6"};
+    static const char* const kUpName[kMaxLevels + 1] = {"", "", "net_up_l2", "net_up_l3", "net_up_l4", "net_up_l5",
+                                                        "net_up_l6"};
     const int L = net->levels;
     State* st = mptr<State>(ws, lay.state);
     const int last_down = std::min(plan.lb - 1, L);   // levels handled by k_down
@@ -599,7 +603,7 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
             constexpr int KM = decltype(km)::value;
             const int grid = persist_grid(l < L ? &k_down<T, KM, true> : &k_down<T, KM, false>, g);
             if (l < L)
-                return launch("net_down", cells, s, [&] {
+                return launch(kDownName[l], cells, s, [&] {
                     k_down<T, KM, true><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), rin, x1, rnext, w, wm, kst, st,
                                                                  cptr<int8_t>(ws, lay.wmode[l][0]));
                 });
@@ -658,7 +662,7 @@ int run_coarse(const nps_net* net, nps_dims d, const Plan& plan, const Layout& l
         NPS_TRY(with_kmode<T>(plan.km[l], [&](auto km) {
             constexpr int KM = decltype(km)::value;
             const int grid = persist_grid(&k_up<T, KM>, g);
-            return launch("net_up", (double)ncells(g), s, [&] {
+            return launch(kUpName[l], (double)ncells(g), s, [&] {
                 k_up<T, KM><<<grid, kBlock, 0, s>>>(cnt, g, full_count(l), xc, x1, xo, w, wm, kst, l - 1, st, nullptr,
                                                     cptr<int8_t>(ws, lay.wmode[l][0]));
             });
