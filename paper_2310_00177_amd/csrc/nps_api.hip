@@ -686,7 +686,8 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
     return with_kmode<T>(plan.km[1], [&](auto km) {
         constexpr int KM = decltype(km)::value;
         if constexpr (is_mfma(KM)) {
-            const int grid = persist_grid_n(&k_down_l1m<KM>, march_columns(g).count() / 2);
+            // as many blocks as fit (the down kernel's registers allow five per CU)
+            const int grid = persist_grid_n(&k_down_l1m<KM>, march_columns(g).count());
             return launch("net_down_l1", (double)ncells(g), s, [&] {
                 k_down_l1m<KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, st,
                                                        cptr<uint32_t>(ws, lay.gmode[0]));
