@@ -145,7 +145,10 @@ def test_precond_parity(kind, shape, L, wkind, precision):
 # 2.6e-3, fp16 2.0e-4 / 3.6e-4; the multilevel blob is exact in both: 1e-7).
 MIXED_BOUNDS = {"mixed_bf16": (6e-3, 8e-3), "mixed_fp16": (7e-4, 8e-4)}
 MIXED_CASES = [("c1", (64, 64, 96), 6, "random_bias"), ("c1", (40, 32, 56), 4, "random_bias"),
-               ("c1", (64, 64, 96), 6, "multilevel")]
+               ("c1", (64, 64, 96), 6, "multilevel"),
+               # a one-tile-wide coarse chain with a 128-cell bottom; random labels (every
+               # window class) with the bottom at level 3
+               ("c1", (32, 32, 64), 4, "random_bias"), ("rand", (16, 32, 64), 3, "random_bias")]
 
 
 @pytest.mark.parametrize("kind,shape,L,wkind", MIXED_CASES)
