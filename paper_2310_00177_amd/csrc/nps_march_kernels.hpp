@@ -37,9 +37,12 @@ enum GroupMode : uint32_t { kGZero = 0, kGPure = 1, kGGeneral = 2 };
 // over a chunk of 4 z-planes (2 on grids with fewer than 1024 such items).
 // Shorter items than the 7-point kernels' keep the per-block work even: an
 // item's cost depends on its group modes (interface footprints cost up to
-// 1.7x empty ones), and block b takes items b, b + G, b + 2G, ... so each
-// block meets a spread of them.  A function of the grid alone: launches and
-// kernels agree on it.
+// 1.7x empty ones) and the cost field is smooth in space.  When the grid of
+// blocks is a multiple of the XCD count, XCD x (blocks b with b % 8 == x)
+// takes the z-chunks zc with zc % 8 == x, every footprint of each, so its
+// blocks share the y halos of a slab in their L2 while every XCD gets slabs
+// from the whole height; its blocks take the XCD's items round-robin.  A
+// function of the grid alone: launches and kernels agree on it.
 __host__ __device__ inline Columns march_columns(Grid g) {
     const int ncx = (g.nx + PX - 1) / PX, ncy = (g.ny + PY - 1) / PY;
     const int chunk = ncx * ncy * ((g.nz + 3) / 4) >= 1024 ? 4 : 2;
@@ -285,8 +288,12 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         return bt;
     };
     bool first = true;
-    for (int wk = blockIdx.x; wk < cl.count(); wk += gridDim.x) {
-        const int cx = wk % cl.ncx, cy = (wk / cl.ncx) % cl.ncy, z0 = (wk / (cl.ncx * cl.ncy)) * cl.chunk;
+    const bool xs = gridDim.x % kXcds == 0;
+    const int xcd = xs ? (int)(blockIdx.x % kXcds) : 0, lstep = xs ? (int)gridDim.x / kXcds : (int)gridDim.x;
+    const int per = cl.ncx * cl.ncy, nzl = xs ? (cl.ncz - xcd + kXcds - 1) / kXcds : cl.ncz, zmul = xs ? kXcds : 1;
+    for (int li = xs ? (int)blockIdx.x / kXcds : (int)blockIdx.x; li < per * nzl; li += lstep) {
+        const int zc = xcd + zmul * (li / per), rest = li % per;
+        const int cx = rest % cl.ncx, cy = rest / cl.ncx, z0 = zc * cl.chunk;
         const int x0 = cx * PX, y0 = cy * PY, z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
         const bool col = xx < g.nx && yy < g.ny;
@@ -410,8 +417,12 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         return u;
     };
     bool first = true;
-    for (int wk = blockIdx.x; wk < cl.count(); wk += gridDim.x) {
-        const int cx = wk % cl.ncx, cy = (wk / cl.ncx) % cl.ncy, z0 = (wk / (cl.ncx * cl.ncy)) * cl.chunk;
+    const bool xs = gridDim.x % kXcds == 0;
+    const int xcd = xs ? (int)(blockIdx.x % kXcds) : 0, lstep = xs ? (int)gridDim.x / kXcds : (int)gridDim.x;
+    const int per = cl.ncx * cl.ncy, nzl = xs ? (cl.ncz - xcd + kXcds - 1) / kXcds : cl.ncz, zmul = xs ? kXcds : 1;
+    for (int li = xs ? (int)blockIdx.x / kXcds : (int)blockIdx.x; li < per * nzl; li += lstep) {
+        const int zc = xcd + zmul * (li / per), rest = li % per;
+        const int cx = rest % cl.ncx, cy = rest / cl.ncx, z0 = zc * cl.chunk;
         const int x0 = cx * PX, y0 = cy * PY, z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
         const bool col = xx < g.nx && yy < g.ny;
