@@ -205,7 +205,8 @@ struct TrainLayout {
     size_t total;
 };
 
-constexpr int kSumBlocks = 256;   // grid of k_image_sums
+constexpr int kSumBlocks = 1024;  // most blocks of k_image_sums (five per CU fit)
+int sum_blocks(Grid g) { return (int)std::min<size_t>(kSumBlocks, std::max<size_t>((ncells(g) + kBlock - 1) / kBlock, 1)); }
 
 TrainLayout make_train_layout(nps_dims d, int levels, int precision, bool solve = false, int n_ortho = 0) {
     TrainLayout t = {};
@@ -549,6 +550,26 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
             };
             using one = std::integral_constant<int, 1>;
             using all = std::integral_constant<int, kTaps>;
+            if constexpr (std::is_same_v<T, float>) {
+                // large levels whose counts are exact in bf16: matrix cores, the
+                // pieces of the solve's FP32 mode or the bf16 leg's single piece
+                if (per_cell && l <= kMfmaMaxLevel) {
+                    const MfmaW* wm = mfma_block(net, blk);
+                    const int mg = elem_grid(((size_t)g.nz * g.ny * ((g.nx + 15) / 16)) * 64);
+                    auto mf = [&](auto km, auto l1) {
+                        constexpr int KM = decltype(km)::value;
+                        constexpr bool L1 = decltype(l1)::value;
+                        return launch("setup_kgen", (double)ncells(g), s, [&] {
+                            k_kgen_store_mfma<KM, L1><<<mg, kBlock, 0, s>>>(img(l), g, wm, out);
+                        });
+                    };
+                    using x3 = std::integral_constant<int, kMfmaBf16x3>;
+                    using b1 = std::integral_constant<int, kMfmaBf16>;
+                    if (bf16w) NPS_TRY(l == 1 ? mf(b1{}, std::true_type{}) : mf(b1{}, std::false_type{}));
+                    else NPS_TRY(l == 1 ? mf(x3{}, std::true_type{}) : mf(x3{}, std::false_type{}));
+                    continue;
+                }
+            }
             if (l == 1) NPS_TRY(per_cell ? go(std::true_type{}, all{}) : go(std::true_type{}, one{}));
             else NPS_TRY(per_cell ? go(std::false_type{}, all{}) : go(std::false_type{}, one{}));
         }
@@ -1389,9 +1410,9 @@ int train_forward(const nps_net* net, const uint8_t* labels, nps_dims d, const T
         double* sp = mptr<double>(ws, tl.spart) + (size_t)(l - 1) * 3 * kTaps * kSumBlocks;
         const double inv_full = std::ldexp(1.0, -3 * (l - 1));
         if (l == 1)
-            NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<true><<<kSumBlocks, kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
+            NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<true><<<sum_blocks(g), kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
         else
-            NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<false><<<kSumBlocks, kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
+            NPS_TRY(launch("train_image_sums", (double)ncells(g), s, [&] { k_image_sums<false><<<sum_blocks(g), kBlock, 0, s>>>(img(l), g, inv_full, sp); }));
     }
     NPS_TRY(run_down_l1<T>(net, labels, d, plan, lay, ws, r, s, bf16w));
     for (int l = 2; l <= L; ++l) {
@@ -1495,7 +1516,7 @@ int train_backward(const nps_net* net, const uint8_t* labels, nps_dims d, const 
         const double* sp = cptr<double>(ws, tl.spart) + (size_t)(l - 1) * 3 * kTaps * kSumBlocks;
         double* ga = grad + off_aff(L, l);
         const double n27 = 27.0 * (double)ncells(g);
-        NPS_TRY(launch("train_aff_grad", 0, s, [&] { k_aff_grad<<<1, 128, 0, s>>>(sp, kSumBlocks, dcl, n27, ga, ga + 82); }));
+        NPS_TRY(launch("train_aff_grad", 0, s, [&] { k_aff_grad<<<3 * kTaps, kBlock, 0, s>>>(sp, sum_blocks(g), dcl, n27, ga, ga + 82); }));
         const Grid gc = level_grid(d, l + 1);
         T* gxc = mptr<T>(ws, tl.gx[l + 1]);
         NPS_TRY(launch("train_bwd_interp", (double)ncells(gc), s, [&] {

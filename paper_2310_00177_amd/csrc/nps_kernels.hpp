@@ -720,6 +720,72 @@ __global__ __launch_bounds__(kBlock) void k_kgen_store(const void* __restrict__ 
     }
 }
 
+// K[t][cell] of one CConv block on a large level (training and the symmetric
+// variant store every level), formed on matrix cores: per 16-cell group along
+// x, K^T[tap][cell] = A[tap][feature] B[feature][cell] as in the solve's
+// kernels (KM = kMfmaBf16x3: three bf16 pieces, the FP32 bar; kMfmaBf16: one
+// piece, the bf16 training leg), B from the 27 window cells' counts (exact in
+// bf16 up to level 3; solid outside the grid).  Lane (g, n) holds taps
+// 16 mb + 4 g + j of cell n and stores them, 16 consecutive cells per tap.
+template <int KM, bool L1>
+__global__ __launch_bounds__(kBlock) void k_kgen_store_mfma(const void* __restrict__ img, Grid g,
+                                                            const MfmaW* __restrict__ wm, float* __restrict__ kst) {
+    constexpr int P = KM == kMfmaBf16x3 ? kPieces : 1;
+    const int lane = threadIdx.x & 63, gl = lane >> 4, n = lane & 15;
+    u16x8 a[P][2][2];
+#pragma unroll
+    for (int p = 0; p < P; ++p)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int ks = 0; ks < 2; ++ks) a[p][mb][ks] = *reinterpret_cast<const u16x8*>(&wm->bf16[p][mb][ks][lane][0]);
+    const size_t ncell = ncells(g);
+    const int nxg = (g.nx + 15) / 16;
+    const size_t ngroups = (size_t)g.nz * g.ny * nxg;
+    const int waves = (int)(gridDim.x * (kBlock / 64));
+    for (size_t grp = (size_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); grp < ngroups; grp += waves) {
+        const int xb = (int)(grp % nxg), y = (int)((grp / nxg) % g.ny), z = (int)(grp / ((size_t)nxg * g.ny));
+        const int x = 16 * xb + n;
+        const bool valid = x < g.nx;
+        uint32_t fw[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {   // window position 16 (j / 4) + 4 g + j % 4 (past 26: zero A rows and columns)
+            const int o = min(16 * (j >> 2) + 4 * gl + (j & 3), kTaps - 1);
+            const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
+            const bool in = valid && in_grid(g, qz, qy, qx);
+            const size_t q = in ? cell_index(g, qz, qy, qx) : 0;
+            const uint32_t v = L1 ? (uint32_t)*at_or(static_cast<const uint8_t*>(img), q, in, g_pad_solid)
+                                  : (in ? static_cast<const uint32_t*>(img)[q] : 0u);
+            fw[j] = feat_word<KM, L1>(v);
+        }
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u16x8 B0 = __builtin_bit_cast(u16x8, (u32x4){fw[0], fw[1], fw[2], fw[3]});
+        const u16x8 B1 = __builtin_bit_cast(u16x8, (u32x4){fw[4], fw[5], fw[6], gl == 2 ? feat_one<KM>() : fw[7]});
+        f32x4 acc[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            acc[mb] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[p][mb][0]),
+                                                                  __builtin_bit_cast(bf16x8, B0), acc[mb], 0, 0, 0);
+                acc[mb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a[p][mb][1]),
+                                                                  __builtin_bit_cast(bf16x8, B1), acc[mb], 0, 0, 0);
+            }
+        }
+        if (valid) {
+            const size_t cell = ((size_t)z * g.ny + y) * g.nx + x;
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int t = 16 * mb + 4 * gl + j;
+                    if (t < kTaps) kst[(size_t)t * ncell + cell] = acc[mb][j];
+                }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // the one-block control kernel
 // ---------------------------------------------------------------------------

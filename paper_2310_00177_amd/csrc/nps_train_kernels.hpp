@@ -454,68 +454,94 @@ __global__ __launch_bounds__(kBlock) void k_wgrad_reduce(const double* __restric
 
 // Image-window sums S[c][o] = sum_p I_c(p + o) of one level (solid padding),
 // the derivative of an Aff scalar with respect to its weights times 27 n_l.
+// The channels are counts times 8^-(l-1), so the fluid and air sums are
+// accumulated as integer counts (exact, in registers); the solid channel
+// follows from I_solid = 1 - I_fluid - I_air, which the padding satisfies
+// too: S[solid][o] = (cells) - S[fluid][o] - S[air][o].  Every partial is a
+// multiple of 8^-(l-1) below 2^32, exact in double, so the sums do not depend
+// on their order.
 template <bool L1>
 __global__ __launch_bounds__(kBlock) void k_image_sums(const void* __restrict__ img, Grid g, double inv_full,
                                                        double* __restrict__ part) {
     const size_t n = ncells(g);
-    double acc[3 * kTaps];
-    for (int i = 0; i < 3 * kTaps; ++i) acc[i] = 0.0;
+    uint32_t s0[kTaps], s1[kTaps], cells = 0;
+#pragma unroll
+    for (int o = 0; o < kTaps; ++o) s0[o] = s1[o] = 0u;
     for (size_t p = (size_t)blockIdx.x * kBlock + threadIdx.x; p < n; p += (size_t)gridDim.x * kBlock) {
         const int x = (int)(p % g.nx), y = (int)((p / g.nx) % g.ny), z = (int)(p / ((size_t)g.nx * g.ny));
+        cells += 1u;
+#pragma unroll
         for (int o = 0; o < kTaps; ++o) {
             const int qz = z + o / 9 - 1, qy = y + (o / 3) % 3 - 1, qx = x + o % 3 - 1;
-            double i0 = 0.0, i1 = 0.0, i2 = 1.0;
             if (in_grid(g, qz, qy, qx)) {
                 const size_t q = cell_index(g, qz, qy, qx);
-                uint32_t c0, c1;
                 const uint32_t v = L1 ? (uint32_t)static_cast<const uint8_t*>(img)[q] : static_cast<const uint32_t*>(img)[q];
+                uint32_t c0, c1;
                 counts_of<L1>(v, c0, c1);
-                i0 = c0 * inv_full;
-                i1 = c1 * inv_full;
-                i2 = 1.0 - i0 - i1;
+                s0[o] += c0;
+                s1[o] += c1;
             }
-            acc[o] += i0;
-            acc[kTaps + o] += i1;
-            acc[2 * kTaps + o] += i2;
         }
     }
-    __shared__ double sh[kBlock / 64];
+    // every wave reduces its sums, then one barrier and one thread per sum
+    // adds the waves in order
+    __shared__ uint32_t sh[kBlock / 64][2 * kTaps + 1];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int i = 0; i < 3 * kTaps; ++i) {
-        const double w = wave_sum(acc[i]);
-        __syncthreads();
-        if (lane == 0) sh[wid] = w;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int k = 0; k < kBlock / 64; ++k) s += sh[k];
-            part[(size_t)blockIdx.x * 3 * kTaps + i] = s;
+    auto wave_total = [](uint32_t v) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += (uint32_t)__shfl_xor((int)v, off, 64);
+        return v;
+    };
+#pragma unroll
+    for (int o = 0; o < kTaps; ++o) {
+        const uint32_t a = wave_total(s0[o]), b = wave_total(s1[o]);
+        if (lane == 0) {
+            sh[wid][o] = a;
+            sh[wid][kTaps + o] = b;
         }
+    }
+    const uint32_t c = wave_total(cells);
+    if (lane == 0) sh[wid][2 * kTaps] = c;
+    __syncthreads();
+    for (int o = threadIdx.x; o < kTaps; o += kBlock) {
+        uint32_t a = 0u, b = 0u, m = 0u;
+        for (int k = 0; k < kBlock / 64; ++k) {
+            a += sh[k][o];
+            b += sh[k][kTaps + o];
+            m += sh[k][2 * kTaps];
+        }
+        double* dst = part + (size_t)blockIdx.x * 3 * kTaps;
+        const double f = (double)a * inv_full, ai = (double)b * inv_full;
+        dst[o] = f;
+        dst[kTaps + o] = ai;
+        dst[2 * kTaps + o] = (double)m - f - ai;
     }
 }
 
 // Aff gradients of one level: dL/dWbar = dL/dc * S / (27 n_l), dL/dBbar = dL/dc,
 // for Aff_1 (dc[0]) and Aff_2 (dc[1]); S summed from the k_image_sums partials.
-__global__ void k_aff_grad(const double* __restrict__ spart, int nparts, const double* __restrict__ dc, double n27,
-                           double* __restrict__ gA1, double* __restrict__ gA2) {
-    for (int i = threadIdx.x; i < 3 * kTaps; i += blockDim.x) {
-        // the partials in block order, U loads in flight per round trip
-        constexpr int U = 16;
-        double s = 0.0;
-        for (int b0 = 0; b0 < nparts; b0 += U) {
-            double t[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) t[u] = b0 + u < nparts ? spart[(size_t)(b0 + u) * 3 * kTaps + i] : 0.0;
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (b0 + u < nparts) s += t[u];
-        }
-        gA1[i] += dc[0] * s / n27;   // Wbar[c][o] with i = c * 27 + o
-        gA2[i] += dc[1] * s / n27;
-    }
+// One block per weight entry e = c * 27 + o (81 blocks): the block adds the
+// entry's partials (exact, see k_image_sums: the order does not matter) and
+// updates its gradient; block 0 also updates Bbar.
+__global__ __launch_bounds__(kBlock) void k_aff_grad(const double* __restrict__ spart, int nparts,
+                                                     const double* __restrict__ dc, double n27,
+                                                     double* __restrict__ gA1, double* __restrict__ gA2) {
+    const int e = blockIdx.x;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nparts; b += kBlock) s += spart[(size_t)b * 3 * kTaps + e];
+    __shared__ double sh[kBlock / 64];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        gA1[3 * kTaps] += dc[0];     // Bbar
-        gA2[3 * kTaps] += dc[1];
+        double t = 0.0;
+        for (int k = 0; k < kBlock / 64; ++k) t += sh[k];
+        gA1[e] += dc[0] * t / n27;   // Wbar[c][o]
+        gA2[e] += dc[1] * t / n27;
+        if (e == 0) {
+            gA1[3 * kTaps] += dc[0];   // Bbar
+            gA2[3 * kTaps] += dc[1];
+        }
     }
 }
 
