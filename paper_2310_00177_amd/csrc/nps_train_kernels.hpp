@@ -68,6 +68,8 @@ __device__ __forceinline__ void accumulate_wgrad_mfma(const float* u_s, const ui
     const int n = lane & 15, k = lane >> 4;
     const int f = 16 * wv + n, o = min(f >> 1, kTaps - 1), ch = f & 1;
     const int off = halo_off_rt(o);
+    // unrolled so that several steps' LDS reads are in flight ahead of their MFMAs
+#pragma unroll 8
     for (int p0 = 0; p0 < kBlock; p0 += 4) {
         const int p = p0 + k;
         const int lx = p % TX, ly = (p / TX) % TY, lz = p / (TX * TY);
@@ -104,6 +106,7 @@ __device__ __forceinline__ void accumulate_wgrad_bf16(const float* u_s, const ui
     const int n = lane & 15, k = lane >> 4;
     const int f = 16 * wv + n, o = min(f >> 1, kTaps - 1), ch = f & 1;
     const int off = halo_off_rt(o);
+#pragma unroll 2
     for (int p0 = 0; p0 < kBlock; p0 += 32) {
         u16x8 b, a[2];
 #pragma unroll
