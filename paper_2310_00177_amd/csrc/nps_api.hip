@@ -551,9 +551,10 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
             using one = std::integral_constant<int, 1>;
             using all = std::integral_constant<int, kTaps>;
             if constexpr (std::is_same_v<T, float>) {
-                // large levels whose counts are exact in bf16: matrix cores, the
-                // pieces of the solve's FP32 mode or the bf16 leg's single piece
-                if (per_cell && l <= kMfmaMaxLevel) {
+                // levels above 4096 cells whose counts are exact in bf16: matrix
+                // cores, the pieces of the solve's FP32 mode or the bf16 leg's
+                // single piece
+                if (ncells(g) > 4096 && l <= kMfmaMaxLevel) {
                     const MfmaW* wm = mfma_block(net, blk);
                     const int mg = elem_grid(((size_t)g.nz * g.ny * ((g.nx + 15) / 16)) * 64);
                     auto mf = [&](auto km, auto l1) {
