@@ -143,6 +143,7 @@ struct Layout {
     size_t dhat, dring[kRing], adring[kRing], x[2], r[2];
     size_t wmode[kMaxLevels + 1][2];   // per-wave CConv modes: [level][down, up (level 1)]
     size_t gmode[2];                   // level 1 on matrix cores: per-group modes [down, up]
+    size_t izero[2];                   // and per-item zero flags [down, up]
     size_t total;
 };
 
@@ -177,6 +178,8 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
     if (is_mfma(p.km[1])) {
         L.gmode[0] = put(group_mode_bytes(level_grid(d, 1)));
         L.gmode[1] = put(group_mode_bytes(level_grid(d, 1)));
+        L.izero[0] = put((size_t)march_columns(level_grid(d, 1)).count());
+        L.izero[1] = put((size_t)march_columns(level_grid(d, 1)).count());
     }
     L.dhat = put(s * n);
     if (solve) {
@@ -515,6 +518,12 @@ int run_setup(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
             k_group_modes<<<(unsigned)((threads + kBlock - 1) / kBlock), kBlock, 0, s>>>(
                 labels, g, mptr<uint8_t>(ws, lay.gmode[0]), mptr<uint8_t>(ws, lay.gmode[1]));
         }));
+        const int items = march_columns(g).count();
+        NPS_TRY(launch("setup_item_zero", (double)items, s, [&] {
+            k_item_zero<<<(unsigned)((items + kBlock - 1) / kBlock), kBlock, 0, s>>>(
+                g, cptr<uint32_t>(ws, lay.gmode[0]), cptr<uint32_t>(ws, lay.gmode[1]), mptr<uint8_t>(ws, lay.izero[0]),
+                mptr<uint8_t>(ws, lay.izero[1]));
+        }));
     }
     for (int l = 1; l <= L; ++l) {
         const Grid g = level_grid(d, l);
@@ -712,7 +721,7 @@ int run_down_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Pla
             const int grid = persist_grid_n(&k_down_l1m<KM>, march_columns(g).count());
             return launch("net_down_l1", (double)ncells(g), s, [&] {
                 k_down_l1m<KM><<<grid, kBlock, 0, s>>>(labels, g, r, x1, rnext, w, wm, st,
-                                                       cptr<uint32_t>(ws, lay.gmode[0]));
+                                                       cptr<uint32_t>(ws, lay.gmode[0]), cptr<uint8_t>(ws, lay.izero[0]));
             });
         } else {
             const int grid = persist_grid(&k_down_l1<T, KM>, g);
@@ -748,7 +757,8 @@ int run_up_l1(const nps_net* net, const uint8_t* labels, nps_dims d, const Plan&
                 return launch("net_up_l1", (double)ncells(g), s, [&] {
                     k_up_l1m<KM, H, H ? 0 : ND><<<grid, kBlock, 0, s>>>(labels, g, x2, x1, dhat, w, wm, st, partials,
                                                                        ad[0], ad[1], ad[2], ad[3],
-                                                                       cptr<uint32_t>(ws, lay.gmode[1]));
+                                                                       cptr<uint32_t>(ws, lay.gmode[1]),
+                                                                       cptr<uint8_t>(ws, lay.izero[1]));
                 });
             };
             if (HOOK || max_dots <= 0) return go(std::integral_constant<int, 0>());

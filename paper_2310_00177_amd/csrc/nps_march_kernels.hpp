@@ -107,6 +107,30 @@ __global__ __launch_bounds__(kBlock) void k_group_modes(const uint8_t* __restric
     }
 }
 
+// One byte per work item (march_columns order), per kernel: 1 when every
+// group of the item's planes is zero for that kernel (down: no window holds
+// fluid; up: no fluid cell).  Such an item only writes its zero outputs.
+__global__ __launch_bounds__(kBlock) void k_item_zero(Grid g, const uint32_t* __restrict__ mdown,
+                                                      const uint32_t* __restrict__ mup, uint8_t* __restrict__ zdown,
+                                                      uint8_t* __restrict__ zup) {
+    const Columns cl = march_columns(g);
+    const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
+    if (i >= cl.count()) return;
+    const int cx = i % cl.ncx, cy = (i / cl.ncx) % cl.ncy, z0 = (i / (cl.ncx * cl.ncy)) * cl.chunk;
+    const int z1 = min(z0 + cl.chunk, g.nz);
+    uint32_t od = 0u, ou = 0u;
+    for (int z = z0; z < z1; ++z) {
+        const size_t row = (((size_t)z * cl.ncy + cy) * cl.ncx + cx) * 4;   // a plane's 16 mode bytes
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            od |= mdown[row + w];
+            ou |= mup[row + w];
+        }
+    }
+    zdown[i] = od == 0u;
+    zup[i] = ou == 0u;
+}
+
 // A wave's MFMA and pure-kernel operands for all its groups.
 template <int KM>
 struct MarchCtx {
@@ -265,7 +289,8 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
                                                      const float* __restrict__ r, float* __restrict__ x1,
                                                      float* __restrict__ rnext, const CConvW<float>* __restrict__ w,
                                                      const MfmaW* __restrict__ wm, const State* st,
-                                                     const uint32_t* __restrict__ gmode) {
+                                                     const uint32_t* __restrict__ gmode,
+                                                     const uint8_t* __restrict__ izero) {
     __shared__ uint2 ring[4 * kPlaneP];
     const int done = st->done;   // tested once the first loads are out
     const MarchCtx<KM> mc = march_ctx<KM>(wm, w);
@@ -297,6 +322,12 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         const int x0 = cx * PX, y0 = cy * PY, z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
         const bool col = xx < g.nx && yy < g.ny;
+        if (izero[zc * per + rest]) {   // no window holds fluid: x1 is zero (read nowhere), and so is the pool
+            if (done) return;
+            for (int c = z0 + 1; c < z1; c += 2)
+                if (((n | gq) & 1) == 0 && col) rnext[cell_index(gc, c >> 1, yy >> 1, xx >> 1)] = 0.0f;
+            continue;
+        }
         const uint32_t* mrow = gmode + ((size_t)cy * cl.ncx + cx) * 4 + wv;   // + z * ncy * ncx * 4 words
         const size_t mstride = (size_t)cl.ncy * cl.ncx * 4;
         const uint32_t own_off = col ? (uint32_t)yy * g.nx + xx : 0u;
@@ -365,7 +396,8 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
                                                    const MfmaW* __restrict__ wm, const State* st,
                                                    double* __restrict__ partials, const float* __restrict__ ad0,
                                                    const float* __restrict__ ad1, const float* __restrict__ ad2,
-                                                   const float* __restrict__ ad3, const uint32_t* __restrict__ gmode) {
+                                                   const float* __restrict__ ad3, const uint32_t* __restrict__ gmode,
+                                                   const uint8_t* __restrict__ izero) {
     static_assert(!HOOK || ND == 0, "the hook forms no dots");
     __shared__ uint2 ring[4 * kPlaneP];
     __shared__ float csh[3][kCPlane];
@@ -426,6 +458,12 @@ __global__ __launch_bounds__(kBlock) NPS_WAVES_PER_EU(KM == kMfmaBf16x3 ? 3 : 4)
         const int x0 = cx * PX, y0 = cy * PY, z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + 16 * wv + n, yy = y0 + gq;
         const bool col = xx < g.nx && yy < g.ny;
+        if (izero[zc * per + rest]) {   // no fluid cell: the output is zero, the dots get nothing
+            if (done) return;
+            if (col)
+                for (int c = z0; c < z1; ++c) dhat[(size_t)c * pstride + (uint32_t)yy * g.nx + xx] = 0.0f;
+            continue;
+        }
         const int own = (gq + 1) * PHX + 16 * wv + n + 1;
         const uint32_t own_off = col ? (uint32_t)yy * g.nx + xx : 0u;
         const uint32_t* mrow = gmode + ((size_t)cy * cl.ncx + cx) * 4 + wv;
