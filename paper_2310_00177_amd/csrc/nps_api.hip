@@ -144,6 +144,7 @@ struct Layout {
     size_t wmode[kMaxLevels + 1][2];   // per-wave CConv modes: [level][down, up (level 1)]
     size_t gmode[2];                   // level 1 on matrix cores: per-group modes [down, up]
     size_t izero[2];                   // and per-item zero flags [down, up]
+    size_t live, items;                // 7-point work items: fluid flags, the list of those with fluid
     size_t total;
 };
 
@@ -191,6 +192,9 @@ Layout make_layout(nps_dims d, int levels, int precision, int n_ortho, bool solv
         L.x[1] = put(x_bytes(precision) * n);
         L.r[0] = put(s * n);   // residuals of alternate iterations (flexible PCG reads both)
         L.r[1] = put(s * n);
+        const size_t nitems = (size_t)columns_of(level_grid(d, 1)).count();
+        L.live = put(nitems);
+        L.items = put(sizeof(uint32_t) * nitems);
     }
     L.total = off;
     return L;
@@ -935,6 +939,27 @@ struct SolverT : Solver {
         NPS_TRY(launch("control", 0, s, [&] {
             k_control<kStageScan><<<1, kCtlBlock, 0, s>>>(st, partials, sgrid, 0, 0, 0, 0, o.tol, 0.0, 0.0, nullptr);
         }));
+        // the 7-point kernels' live items; the others get zeros in the vectors
+        // those kernels write (and read back) there
+        const Grid g = level_grid(d, 1);
+        const int nitems = columns_of(g).count();
+        ZeroBufs zb{};
+        auto zero = [&](void* p, int bytes) {
+            zb.p[zb.n] = p;
+            zb.bytes[zb.n++] = bytes;
+        };
+        zero(mptr<X>(ws, lay.x[1]), (int)sizeof(X));
+        zero(mptr<T>(ws, lay.r[0]), (int)sizeof(T));
+        zero(mptr<T>(ws, lay.r[1]), (int)sizeof(T));
+        for (int i = 0; i <= o.n_ortho; ++i) {
+            zero(mptr<T>(ws, lay.dring[i]), (int)sizeof(T));
+            zero(mptr<T>(ws, lay.adring[i]), (int)sizeof(T));
+        }
+        uint8_t* live = mptr<uint8_t>(ws, lay.live);
+        NPS_TRY(launch("setup_items", (double)n, s, [&] { k_item_live<<<nitems, kBlock, 0, s>>>(labels, g, live, zb); }));
+        NPS_TRY(launch("setup_item_list", 0, s, [&] {
+            k_item_list<<<1, kBlock, 0, s>>>(live, nitems, mptr<uint32_t>(ws, lay.items), st);
+        }));
         NPS_HIP(hipMemcpyAsync(hs, st, sizeof(State), hipMemcpyDeviceToHost, s));
         return NPS_OK;
     }
@@ -942,18 +967,21 @@ struct SolverT : Solver {
     int enqueue_setup() override {
         hf->done = 0;
         hf->iter = 0;
+        nlive = hs->nlive;   // the validation copy has completed
         return run_setup<T>(net, labels, d, plan, lay, ws, s);
     }
 
+    int nlive = 0;   // live items of the 7-point kernels (set-up)
+
     // The ortho kernel's grid (the count of its partials, which the next
     // body's residual kernel sums).
-    int ortho_grid(Grid g) const {
+    int ortho_grid() const {
         switch (o.n_ortho) {
-            case 0: return persist_grid_n(&k_ortho<T, 0>, columns_of(g).count());
-            case 1: return persist_grid_n(&k_ortho<T, 1>, columns_of(g).count());
-            case 2: return persist_grid_n(&k_ortho<T, 2>, columns_of(g).count());
-            case 3: return persist_grid_n(&k_ortho<T, 3>, columns_of(g).count());
-            default: return persist_grid_n(&k_ortho<T, 4>, columns_of(g).count());
+            case 0: return persist_grid_n(&k_ortho<T, 0>, nlive);
+            case 1: return persist_grid_n(&k_ortho<T, 1>, nlive);
+            case 2: return persist_grid_n(&k_ortho<T, 2>, nlive);
+            case 3: return persist_grid_n(&k_ortho<T, 3>, nlive);
+            default: return persist_grid_n(&k_ortho<T, 4>, nlive);
         }
     }
 
@@ -995,14 +1023,16 @@ struct SolverT : Solver {
         // (from body 2 on it first runs the Step stage of the previous body, on
         // the ortho kernel's partials; its own ||r||^2 partials go to the dots
         // buffer, which the Residual stage consumes before the up kernel refills it)
-        const int np_res = persist_grid_n(&k_residual<T, X>, columns_of(g).count());
-        const int snp = k > 1 ? ortho_grid(g) : 0;
+        const uint32_t* items = cptr<uint32_t>(ws, lay.items);
+        const int np_res = persist_grid_n(&k_residual<T, X>, nlive);
+        const int snp = k > 1 ? ortho_grid() : 0;
         NPS_TRY(launch("residual", cells, s, [&] {
             // body k reads the iterate from buffer (k - 1) & 1 (state.xcur, which
             // every Residual stage flips) and writes the other
             const bool odd = ((k - 1) & 1) != 0;
             k_residual<T, X><<<np_res, kBlock, 0, s>>>(labels, g, b, odd ? x1b : x0, odd ? x0 : x1b, dpend, r, st,
-                                                       partials, snp, ((k - 1) % R + R) % R, hf_d, pdots);
+                                                       partials, snp, ((k - 1) % R + R) % R, hf_d, pdots, items,
+                                                       nlive);
         }));
         // The Residual stage (convergence test, 1/||r||, the dots the up
         // kernel forms) is first needed by the up sweep, and the network is
@@ -1029,12 +1059,12 @@ struct SolverT : Solver {
         }
         // the Dots stage runs inside the ortho kernel (every block sums the dots)
         const int dnp = o.n_ortho > 0 ? np : 0;
-        const int ogrid = ortho_grid(g);
+        const int ogrid = ortho_grid();
         NPS_TRY(launch("ortho_matvec", cells, s, [&] {
             auto go = [&](auto no) {
                 k_ortho<T, decltype(no)::value><<<ogrid, kBlock, 0, s>>>(labels, g, dhat, dp[0], dp[1], dp[2], dp[3], r,
                                                                          dk, adk, st, pdots, dnp, sl[0], sl[1], sl[2],
-                                                                         sl[3], partials);
+                                                                         sl[3], partials, items, nlive);
             };
             switch (o.n_ortho) {
                 case 0: go(std::integral_constant<int, 0>{}); break;

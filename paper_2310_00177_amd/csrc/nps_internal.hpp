@@ -95,6 +95,7 @@ struct State {
     int sym;                   // 1: preconditioner P^T o P (the symmetric variant)
     int ndots;                 // partial dots the level-1 up kernel forms this iteration
     double rho, rho_prev;      // PCG forms: r . P(r)/||r|| of this and of the previous iteration
+    int nlive;                 // work items of the 7-point kernels that hold fluid
 };
 
 // Tile geometry of the stencil kernels: TX x TY x TZ cells, one per thread.

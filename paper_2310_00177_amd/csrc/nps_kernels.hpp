@@ -1656,6 +1656,70 @@ __host__ __device__ inline Columns columns_of(Grid g) {
     return Columns{ncx, ncy, (g.nz + chunk - 1) / chunk, chunk};
 }
 
+// Work items of the 7-point kernels that hold no fluid cell.  On such an
+// item r = 0 and A d = 0, and it adds nothing to any dot (every term has a
+// factor r or A d), so once its cells hold zeros in the solver's vectors the
+// kernels need not visit it: they walk a list of the other ("live") items.
+// Buffers zeroed on the items without fluid at set-up (2, 4 or 8 B elements).
+struct ZeroBufs {
+    void* p[2 * kRing + 3];
+    int bytes[2 * kRing + 3];
+    int n;
+};
+
+// One block per item (a thread per column, columns_of order): live[w] = 1
+// when item w holds a fluid cell; otherwise the item's cells are zeroed in
+// every buffer of zb.
+__global__ __launch_bounds__(kBlock) void k_item_live(const uint8_t* __restrict__ lab, Grid g,
+                                                      uint8_t* __restrict__ live, ZeroBufs zb) {
+    const Columns cl = columns_of(g);
+    const int w = blockIdx.x;
+    const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
+    const int z1 = min(z0 + cl.chunk, g.nz);
+    const int xx = x0 + threadIdx.x % PX, yy = y0 + threadIdx.x / PX;
+    const bool col = xx < g.nx && yy < g.ny;
+    int f = 0;
+    if (col)
+        for (int z = z0; z < z1; ++z) f |= lab[cell_index(g, z, yy, xx)] == kFluid;
+    const int any = __syncthreads_or(f);
+    if (threadIdx.x == 0) live[w] = any ? 1 : 0;
+    if (any || !col) return;
+    for (int i = 0; i < zb.n; ++i)
+        for (int z = z0; z < z1; ++z) {
+            const size_t q = cell_index(g, z, yy, xx);
+            if (zb.bytes[i] == 8) static_cast<double*>(zb.p[i])[q] = 0.0;
+            else if (zb.bytes[i] == 4) static_cast<float*>(zb.p[i])[q] = 0.0f;
+            else static_cast<uint16_t*>(zb.p[i])[q] = 0;
+        }
+}
+
+// One block: items[0 .. nlive) = the live items in increasing order (z-major,
+// so each XCD's contiguous share of the list is a z-range), st->nlive = nlive.
+__global__ __launch_bounds__(kBlock) void k_item_list(const uint8_t* __restrict__ live, int count,
+                                                      uint32_t* __restrict__ items, State* st) {
+    constexpr int W = kBlock / 64;
+    __shared__ uint32_t wsum[W];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t base = 0;
+    for (int i0 = 0; i0 < count; i0 += kBlock) {
+        const int i = i0 + threadIdx.x;
+        const bool f = i < count && live[i] != 0;
+        const uint64_t m = __ballot(f);
+        if (lane == 0) wsum[wv] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t off = base, tot = 0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            off += k < wv ? wsum[k] : 0u;
+            tot += wsum[k];
+        }
+        if (f) items[off + (uint32_t)__popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)i;
+        base += tot;
+        __syncthreads();   // wsum is rewritten by the next round
+    }
+    if (threadIdx.x == 0) st->nlive = (int)base;
+}
+
 // d = dhat - sum_j beta_j d_(k-1-j) (classical Gram-Schmidt in the A inner
 // product; equal to the paper's sequential update because the directions in
 // the window are already mutually A-orthogonal), A d, and the partial dots
@@ -1666,14 +1730,16 @@ __host__ __device__ inline Columns columns_of(Grid g) {
 // own from the dnparts partials of the dots (the same sums in every block:
 // a fixed order); block 0 records them in the state.  dots and partials
 // must be different buffers (blocks write their partials while others may
-// still read the dots).
+// still read the dots).  Only the live items are visited (items[0 .. nlive));
+// the others hold d = 0 and A d = 0 from set-up.
 template <class T, int NO>
 __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ lab, Grid g, const T* __restrict__ dhat,
                                                   const T* __restrict__ p0, const T* __restrict__ p1,
                                                   const T* __restrict__ p2, const T* __restrict__ p3,
                                                   const T* __restrict__ r, T* __restrict__ dout, T* __restrict__ adout,
                                                   State* st, const double* __restrict__ dots, int dnparts, int sl0,
-                                                  int sl1, int sl2, int sl3, double* __restrict__ partials) {
+                                                  int sl1, int sl2, int sl3, double* __restrict__ partials,
+                                                  const uint32_t* __restrict__ items, int nlive) {
     __shared__ uint32_t lab_s[2][kPlaneP];
     __shared__ T d_s[2][kPlaneP];
     __shared__ double beta_s[kMaxOrtho];
@@ -1712,9 +1778,38 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * e.p[j] : dv;
         return dv;
     };
+    // The Dots stage, once per block (its loads behind the first item's first
+    // planes); false: the solve has stopped and the block writes nothing.
+    auto start = [&]() -> bool {
+        if (done) return false;
+        if (dnparts > 0) {
+            // the up kernel forms ndots <= max(NO, 2) dots (NPSDO: nprev
+            // <= n_ortho; the PCG forms: 1 or 2)
+            constexpr int DW = NO > 2 ? NO : 2;
+            double dw[DW], dv[kMaxOrtho] = {0.0, 0.0, 0.0, 0.0};
+            sum_partials<DW, kBlock>(dots, dnparts, ndots, dw);
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int j = 0; j < DW; ++j) dv[j] = dw[j];
+                double beta[kMaxOrtho], rho;
+                dots_betas(din, dv, beta, rho);
+#pragma unroll
+                for (int j = 0; j < kMaxOrtho; ++j) beta_s[j] = beta[j];
+                if (blockIdx.x == 0) {
+#pragma unroll
+                    for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
+                    if (din.method != 0) st->rho = rho;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < kMaxOrtho; ++j) bj[j] = (T)beta_s[j];
+        }
+        return true;
+    };
     bool first = true;
-    for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int w = sp.t0;
+    for (TileSpan sp = tile_span(nlive); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int w = (int)items[sp.t0];
         const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
         const int z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + lx, yy = y0 + ly;
@@ -1724,31 +1819,8 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         auto pre2 = plane(x0, y0, z0 + 1);
         if (first) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
-            if (done) return;
             first = false;
-            if (dnparts > 0) {   // the Dots stage, its loads behind the first plane's
-                // the up kernel forms ndots <= max(NO, 2) dots (NPSDO: nprev
-                // <= n_ortho; the PCG forms: 1 or 2)
-                constexpr int DW = NO > 2 ? NO : 2;
-                double dw[DW], dv[kMaxOrtho] = {0.0, 0.0, 0.0, 0.0};
-                sum_partials<DW, kBlock>(dots, dnparts, ndots, dw);
-                if (threadIdx.x == 0) {
-#pragma unroll
-                    for (int j = 0; j < DW; ++j) dv[j] = dw[j];
-                    double beta[kMaxOrtho], rho;
-                    dots_betas(din, dv, beta, rho);
-#pragma unroll
-                    for (int j = 0; j < kMaxOrtho; ++j) beta_s[j] = beta[j];
-                    if (blockIdx.x == 0) {
-#pragma unroll
-                        for (int j = 0; j < kMaxOrtho; ++j) st->beta[j] = beta[j];
-                        if (din.method != 0) st->rho = rho;
-                    }
-                }
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < kMaxOrtho; ++j) bj[j] = (T)beta_s[j];
-            }
+            if (!start()) return;
         }
         T dm = direction(below);   // own column, plane s - 2
         uint32_t lm = below.l;
@@ -1799,6 +1871,7 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
             if (s + 1 <= z1) step(s + 1, pre2);
         }
     }
+    if (first && !start()) return;   // a block without items
     block_partials<kBlock>(v, partials);
 }
 
@@ -1809,7 +1882,8 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
 // iteration, and the Residual stage flips state.xcur to match) and r as the
 // network input, and the partial ||r||^2.  Plane-marching: step s stages
 // plane s (x + alpha d and the labels, outside the grid x = 0 and solid)
-// and forms plane s - 1.
+// and forms plane s - 1.  Only the live items are visited (items[0 .. nlive),
+// k_item_list); the others hold r = 0 and x = 0 from set-up.
 // With snp > 0 the kernel first runs the previous iteration's Step stage:
 // every block sums the snp partials of d . A d and r . d (the same sums in
 // each, a fixed order), forms alpha and applies the update; block 0 records
@@ -1820,7 +1894,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
                                                      const double* __restrict__ b, const X* __restrict__ x,
                                                      X* __restrict__ xnew, const T* __restrict__ dpend,
                                                      T* __restrict__ r, State* st, const double* __restrict__ steps,
-                                                     int snp, int slot, HostFlags* hf, double* partials) {
+                                                     int snp, int slot, HostFlags* hf, double* partials,
+                                                     const uint32_t* __restrict__ items, int nlive) {
     __shared__ uint32_t lab_s[2][kPlaneP];
     __shared__ X x_s[2][kPlaneP];
     __shared__ double alpha_s;
@@ -1843,9 +1918,29 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         return load_batch<kPlane, XDL<X, T>>([&](int i) { return element(zz, y0 + i / PHX - 1, x0 + i % PHX - 1); });
     };
     auto updated = [&](const XDL<X, T>& e) { return pend ? e.x + alpha * (X)e.d : e.x; };
+    // The Step stage, once per block (its loads behind the first item's first
+    // planes); false: the solve has stopped or broken down, and the block
+    // writes nothing.
+    auto start = [&]() -> bool {
+        if (done) return false;
+        if (pend) {
+            double sv[2];
+            sum_partials<2, kBlock>(steps, snp, 2, sv);
+            if (threadIdx.x == 0) {
+                double a = 0.0;
+                ok_s = step_alpha(sin, sv[0], sv[1], a);
+                alpha_s = a;
+                if (blockIdx.x == 0) step_update(st, sin, slot, sv[0], sv[1], hf);
+            }
+            __syncthreads();
+            if (!ok_s) return false;
+            alpha = (X)alpha_s;
+        }
+        return true;
+    };
     bool first = true;
-    for (TileSpan sp = tile_span(cl.count()); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int w = sp.t0;
+    for (TileSpan sp = tile_span(nlive); sp.t0 < sp.t1; sp.t0 += sp.step) {
+        const int w = (int)items[sp.t0];
         const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
         const int z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + lx, yy = y0 + ly;
@@ -1855,21 +1950,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         auto pre2 = plane(x0, y0, z0 + 1);
         if (first) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
-            if (done) return;
             first = false;
-            if (pend) {   // the Step stage, its loads behind the first plane's
-                double v[2];
-                sum_partials<2, kBlock>(steps, snp, 2, v);
-                if (threadIdx.x == 0) {
-                    double a = 0.0;
-                    ok_s = step_alpha(sin, v[0], v[1], a);
-                    alpha_s = a;
-                    if (blockIdx.x == 0) step_update(st, sin, slot, v[0], v[1], hf);
-                }
-                __syncthreads();
-                if (!ok_s) return;
-                alpha = (X)alpha_s;
-            }
+            if (!start()) return;
         }
         X xm = updated(below);   // own column, plane s - 2
         uint32_t lm = below.l;
@@ -1920,7 +2002,8 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
             if (s + 1 <= z1) step(s + 1, pre2);
         }
     }
-    if (!first || !done) block_partials<kBlock>(v, partials);
+    if (first && !start()) return;   // a block without items
+    block_partials<kBlock>(v, partials);
 }
 
 // Partial dots v . a_j, j < the state's ndots (the up kernel's dots, for the
