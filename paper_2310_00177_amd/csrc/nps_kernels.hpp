@@ -27,6 +27,7 @@
 #include "nps_internal.hpp"
 
 #include <cmath>
+#include <type_traits>
 
 namespace nps {
 
@@ -826,19 +827,35 @@ constexpr int ctl_width() {
          : STAGE == kStageDots ? kMaxOrtho : STAGE == kStageLoss ? 1 : 2;
 }
 
-// Sum of rows w < rows (of W) of nparts per-block partials (structure of
-// arrays, block order, a fixed reduction tree for a given NT), left in v of
-// thread 0 of a block of NT threads.  Every thread must call it.
-// Each thread issues U partials per row before adding any: one memory
-// latency per U NT partials (a load-add loop would wait for every load in
-// turn).
+// Partial sums (sum_partials below) in two parts: head_partials issues the
+// first round of loads (partials b < kSumU NT, every row w < W, which must lie
+// inside the buffer) ahead of other work, finish_partials adds them and the
+// rest.  Every thread of the block calls both.
+constexpr int kSumU = 4;
+
 template <int W, int NT>
-__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int nparts, int rows, double (&v)[W]) {
-    constexpr int U = 4;
+__device__ __forceinline__ void head_partials(const double* __restrict__ partials, int nparts,
+                                              double (&t)[W][kSumU]) {
+#pragma unroll
+    for (int u = 0; u < kSumU; ++u) {
+        const int b = u * NT + (int)threadIdx.x;
+#pragma unroll
+        for (int w = 0; w < W; ++w) t[w][u] = b < nparts ? partials[(size_t)w * kMaxRedBlocks + b] : 0.0;
+    }
+}
+
+template <int W, int NT>
+__device__ __forceinline__ void finish_partials(const double (&t0)[W][kSumU], const double* __restrict__ partials,
+                                                int nparts, int rows, double (&v)[W]) {
+    constexpr int U = kSumU;
     __shared__ double sh[W][NT / 64];
 #pragma unroll
     for (int w = 0; w < W; ++w) v[w] = 0.0;
-    for (int b0 = 0; b0 < nparts; b0 += U * NT) {
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int w = 0; w < W; ++w) v[w] += w < rows ? t0[w][u] : 0.0;
+    for (int b0 = U * NT; b0 < nparts; b0 += U * NT) {
         double t[W][U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -868,6 +885,19 @@ __device__ __forceinline__ void sum_partials(const double* __restrict__ partials
             v[w] = t;
         }
     }
+}
+
+// Sum of rows w < rows (of W) of nparts per-block partials (structure of
+// arrays, block order, a fixed reduction tree for a given NT), left in v of
+// thread 0 of a block of NT threads.  Every thread must call it.
+// Each thread issues kSumU partials per row before adding any: one memory
+// latency per kSumU NT partials (a load-add loop would wait for every load in
+// turn).
+template <int W, int NT>
+__device__ __forceinline__ void sum_partials(const double* __restrict__ partials, int nparts, int rows, double (&v)[W]) {
+    double t[W][kSumU];
+    head_partials<W, NT>(partials, nparts, t);
+    finish_partials<W, NT>(t, partials, nparts, rows, v);
 }
 
 // The state the Dots stage reads (sl: ring slots of d_(k-1), d_(k-2), ...),
@@ -1778,16 +1808,18 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         for (int j = 0; j < NO; ++j) dv = j < nprev ? dv - bj[j] * e.p[j] : dv;
         return dv;
     };
-    // The Dots stage, once per block (its loads behind the first item's first
-    // planes); false: the solve has stopped and the block writes nothing.
+    // The Dots stage, once per block (its partials loaded first, the first
+    // item's loads issued behind them); false: the solve has stopped and the
+    // block writes nothing.  The up kernel forms ndots <= max(NO, 2) dots
+    // (NPSDO: nprev <= n_ortho; the PCG forms: 1 or 2).
+    constexpr int DW = NO > 2 ? NO : 2;
+    double dpart[DW][kSumU];
+    head_partials<DW, kBlock>(dots, dnparts, dpart);
     auto start = [&]() -> bool {
         if (done) return false;
         if (dnparts > 0) {
-            // the up kernel forms ndots <= max(NO, 2) dots (NPSDO: nprev
-            // <= n_ortho; the PCG forms: 1 or 2)
-            constexpr int DW = NO > 2 ? NO : 2;
             double dw[DW], dv[kMaxOrtho] = {0.0, 0.0, 0.0, 0.0};
-            sum_partials<DW, kBlock>(dots, dnparts, ndots, dw);
+            finish_partials<DW, kBlock>(dpart, dots, dnparts, ndots, dw);
             if (threadIdx.x == 0) {
 #pragma unroll
                 for (int j = 0; j < DW; ++j) dv[j] = dw[j];
@@ -1807,9 +1839,10 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         }
         return true;
     };
-    bool first = true;
-    for (TileSpan sp = tile_span(nlive); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int w = (int)items[sp.t0];
+    // One work item; the block's first (FIRST) runs the Dots stage once its
+    // loads are out (false: the block stops).  The first item is peeled off the
+    // loop, so the stage's registers are free during the others.
+    auto item = [&](int w, auto first_tag) -> bool {
         const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
         const int z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + lx, yy = y0 + ly;
@@ -1817,10 +1850,9 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
         const LD below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
         auto pre = plane(x0, y0, z0);
         auto pre2 = plane(x0, y0, z0 + 1);
-        if (first) {
+        if constexpr (decltype(first_tag)::value) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
-            first = false;
-            if (!start()) return;
+            if (!start()) return false;
         }
         T dm = direction(below);   // own column, plane s - 2
         uint32_t lm = below.l;
@@ -1870,8 +1902,15 @@ __global__ __launch_bounds__(kBlock) void k_ortho(const uint8_t* __restrict__ la
             step(s, pre);
             if (s + 1 <= z1) step(s + 1, pre2);
         }
+        return true;
+    };
+    TileSpan sp = tile_span(nlive);
+    if (sp.t0 >= sp.t1) {   // a block without items
+        if (!start()) return;
+    } else {
+        if (!item((int)items[sp.t0], std::true_type{})) return;
+        for (sp.t0 += sp.step; sp.t0 < sp.t1; sp.t0 += sp.step) item((int)items[sp.t0], std::false_type{});
     }
-    if (first && !start()) return;   // a block without items
     block_partials<kBlock>(v, partials);
 }
 
@@ -1918,14 +1957,16 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         return load_batch<kPlane, XDL<X, T>>([&](int i) { return element(zz, y0 + i / PHX - 1, x0 + i % PHX - 1); });
     };
     auto updated = [&](const XDL<X, T>& e) { return pend ? e.x + alpha * (X)e.d : e.x; };
-    // The Step stage, once per block (its loads behind the first item's first
-    // planes); false: the solve has stopped or broken down, and the block
-    // writes nothing.
+    // The Step stage, once per block (its partials loaded first, the first
+    // item's loads issued behind them); false: the solve has stopped or broken
+    // down, and the block writes nothing.
+    double spart[2][kSumU];
+    head_partials<2, kBlock>(steps, pend ? snp : 0, spart);
     auto start = [&]() -> bool {
         if (done) return false;
         if (pend) {
             double sv[2];
-            sum_partials<2, kBlock>(steps, snp, 2, sv);
+            finish_partials<2, kBlock>(spart, steps, snp, 2, sv);
             if (threadIdx.x == 0) {
                 double a = 0.0;
                 ok_s = step_alpha(sin, sv[0], sv[1], a);
@@ -1938,9 +1979,10 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         }
         return true;
     };
-    bool first = true;
-    for (TileSpan sp = tile_span(nlive); sp.t0 < sp.t1; sp.t0 += sp.step) {
-        const int w = (int)items[sp.t0];
+    // One work item; the block's first (FIRST) runs the Step stage once its
+    // loads are out (false: the block stops).  The first item is peeled off the
+    // loop, so the stage's registers are free during the others.
+    auto item = [&](int w, auto first_tag) -> bool {
         const int x0 = (w % cl.ncx) * PX, y0 = ((w / cl.ncx) % cl.ncy) * PY, z0 = (w / (cl.ncx * cl.ncy)) * cl.chunk;
         const int z1 = min(z0 + cl.chunk, g.nz);
         const int xx = x0 + lx, yy = y0 + ly;
@@ -1948,10 +1990,9 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
         const XDL<X, T> below = element(z0 - 1, yy, xx);   // the z - 1 neighbour of plane z0
         auto pre = plane(x0, y0, z0);
         auto pre2 = plane(x0, y0, z0 + 1);
-        if (first) {
+        if constexpr (decltype(first_tag)::value) {
             __asm__ volatile("" ::: "memory");   // the loads stay above the test
-            first = false;
-            if (!start()) return;
+            if (!start()) return false;
         }
         X xm = updated(below);   // own column, plane s - 2
         uint32_t lm = below.l;
@@ -2001,8 +2042,15 @@ __global__ __launch_bounds__(kBlock) void k_residual(const uint8_t* __restrict__
             step(s, pre);
             if (s + 1 <= z1) step(s + 1, pre2);
         }
+        return true;
+    };
+    TileSpan sp = tile_span(nlive);
+    if (sp.t0 >= sp.t1) {   // a block without items
+        if (!start()) return;
+    } else {
+        if (!item((int)items[sp.t0], std::true_type{})) return;
+        for (sp.t0 += sp.step; sp.t0 < sp.t1; sp.t0 += sp.step) item((int)items[sp.t0], std::false_type{});
     }
-    if (first && !start()) return;   // a block without items
     block_partials<kBlock>(v, partials);
 }
 
