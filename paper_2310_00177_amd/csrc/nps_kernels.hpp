@@ -1552,13 +1552,17 @@ __device__ __forceinline__ T bottom_interp(const T* xc, const BottomLevel& vc, i
 // on the way up.
 template <class T>
 __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, State* st) {
-    const int done = st->done;   // tested once the loads below are out
+    const int done = st->done;   // tested once the network is formed
     const ResidualIn rin = residual_in(st);   // read by the Residual stage below
     __shared__ T buf[kBottomLds];
     const int lb = a.lb, L = a.L, p = threadIdx.x;
     const BottomLevel v0 = a.lv[lb];
     const int n0 = v0.n, n1 = lb < L ? a.lv[lb + 1].n : 1;
     const int q0 = min(p, n0 - 1), q1 = min(p, n1 - 1);   // clamped: every load is in bounds
+    // All loads go out at once: the Residual stage's partials (its sums are
+    // only needed at the end), the input and the stored kernels.
+    double rpart[1][kSumU];
+    head_partials<1, kBottomThreads>(a.res_partials, a.res_partials ? a.res_nparts : 0, rpart);
     T r0 = ld_global(a.rin + q0);
     // the combination weights of level lb (set up before the solve)
     const T c1_0 = (T)st->c1[lb - 1], c2_0 = (T)st->c2[lb - 1];
@@ -1570,16 +1574,6 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
         for (int t = 0; t < kTaps; ++t) k2_0[t] = ld_global(a.k2[lb] + (size_t)t * n0 + q0);
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) k1_1[t] = ld_global(a.k1[lb + 1] + (size_t)t * n1 + q1);
-    }
-    __asm__ volatile("" ::: "memory");   // the loads stay above the test
-    if (done) return;
-    if (a.res_partials) {   // the Residual stage (its loads go out behind the ones above)
-        __shared__ int done_s;
-        double v[1];
-        sum_partials<1, kBottomThreads>(a.res_partials, a.res_nparts, 1, v);
-        if (p == 0) done_s = residual_stage(st, rin, v[0], a.hf);
-        __syncthreads();
-        if (done_s) return;
     }
     // zero borders: clear the whole buffer, then fill the interiors
     for (int i = p; i < a.used; i += kBottomThreads) buf[i] = T(0);
@@ -1650,6 +1644,18 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
             *xo = c1 * *xo + c2 * acc;
         }
         if (l > lb) __syncthreads();   // level lb's cells are read back only by the thread that wrote them
+    }
+    // The network is linear in r, so the stop test and the Residual stage
+    // (convergence, 1/||r||, read from the next kernel on) come last: a block
+    // of a stopped solve writes nothing.
+    if (done) return;
+    if (a.res_partials) {
+        __shared__ int done_s;
+        double v[1];
+        finish_partials<1, kBottomThreads>(rpart, a.res_partials, a.res_nparts, 1, v);
+        if (p == 0) done_s = residual_stage(st, rin, v[0], a.hf);
+        __syncthreads();
+        if (done_s) return;
     }
     if (p < n0) a.xout[p] = buf[v0.x1 + c0];   // x^lb (x1^L itself when the bottom holds only the coarsest level)
 }
