@@ -24,7 +24,9 @@
  *     it; nps_solve synchronises with it before returning, the parity hooks
  *     do not.
  *   - No solve-path call allocates device memory: scratch comes from the
- *     caller's workspace, sized by nps_workspace_bytes.
+ *     caller's workspace, sized by nps_workspace_bytes.  Its contents on
+ *     entry do not matter (each call writes what it later reads), so one
+ *     workspace may serve any sequence of calls on one stream.
  *   - Return value: NPS_OK (0), a soft status (> 0: outputs valid), or a
  *     hard error (< 0: outputs untouched).  nps_last_error() returns a
  *     thread-local message for the last failure.
