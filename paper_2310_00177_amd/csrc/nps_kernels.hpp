@@ -1569,11 +1569,16 @@ __global__ __launch_bounds__(kBottomThreads) void k_bottom(BottomArgs<T> a, Stat
     T k1_0[kTaps], k2_0[kTaps], k1_1[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) k1_0[t] = ld_global(a.k1[lb] + (size_t)t * n0 + q0);
-    if (lb < L) {
+    if (lb < L) {   // in the order of use; level lb + 1's kernel only for its cells (whole waves skip it)
+        if (p < n1) {
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) k1_1[t] = ld_global(a.k1[lb + 1] + (size_t)t * n1 + q1);
+        } else {
+#pragma unroll
+            for (int t = 0; t < kTaps; ++t) k1_1[t] = T(0);
+        }
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) k2_0[t] = ld_global(a.k2[lb] + (size_t)t * n0 + q0);
-#pragma unroll
-        for (int t = 0; t < kTaps; ++t) k1_1[t] = ld_global(a.k1[lb + 1] + (size_t)t * n1 + q1);
     }
     // zero borders: clear the whole buffer, then fill the interiors
     for (int i = p; i < a.used; i += kBottomThreads) buf[i] = T(0);
